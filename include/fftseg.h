@@ -1,0 +1,173 @@
+/*
+ * fftseg -- batched 1-D complex FFTs over the fixed-length segments of a
+ * long signal, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Tsiomenko & Rees, "Accelerating Fast Fourier Transforms Using
+ * Hadoop and CUDA", arXiv:1407.6915):
+ *   Sec. III   a very large signal is cut into consecutive fixed-length FFT
+ *              segments, each an <offset, FFT segment> record whose offset
+ *              is the byte offset from the start of the signal; a whole block
+ *              of such segments moves to the GPU in one allocate+copy pair
+ *              and one batched plan transforms every segment of the block;
+ *              the transform may run in place; outputs are kept in the
+ *              order (position) of their inputs.
+ *   Sec. I-II  the transform is the Cooley-Tukey FFT, i.e. exactly the DFT
+ *                 X_s[k] = sum_{n<N} x_s[n] exp(d 2 pi i n k / N),
+ *              d = -1 forward, +1 inverse, no normalisation.
+ *   Sec. II, III  data larger than device memory is moved between host and
+ *              device in few, large transfers (streaming entry point below).
+ *
+ * Data layout: a batch is `batch` consecutive segments of `segment_len`
+ * complex64 samples (interleaved float32 re, im; 8 bytes per sample), row
+ * major [batch][segment_len].  The record at byte offset s*segment_len*8 of
+ * the input yields its spectrum at the same byte offset of the output, in
+ * natural frequency order k = 0..segment_len-1.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named in/out/base are DEVICE pointers (hipMalloc'd memory or
+ *    a sub-range of it) and stay owned by the caller; they must stay valid
+ *    until the work enqueued on `stream` has run.  They must be 8-byte
+ *    aligned; 16-byte alignment is not required.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Exec calls only enqueue work and return.
+ *  - Every call returns an fft_status_t (or NULL for constructors) and never
+ *    aborts.  On failure fft_last_status()/fft_last_error() of the calling
+ *    thread hold the status and a message (with hipGetErrorString text for
+ *    FFT_ERR_HIP).  All argument checks happen before any device work.
+ *  - Supported lengths: 1 <= segment_len <= 2^24 whose prime factors are
+ *    2, 3 and 5.  Other lengths give FFT_ERR_UNSUPPORTED_LENGTH.
+ *  - A plan may be used from one thread at a time and has at most one exec
+ *    in flight (long-segment plans own a scratch buffer); create one plan
+ *    per concurrent stream.
+ */
+#ifndef FFTSEG_H
+#define FFTSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFT_FORWARD (-1) /* exp(-2 pi i n k / N) */
+#define FFT_INVERSE (+1) /* exp(+2 pi i n k / N), unnormalised */
+
+typedef enum {
+    FFT_OK = 0,
+    FFT_ERR_INVALID_ARG = -1,        /* zero/overflowing size, bad direction, NULL */
+    FFT_ERR_UNSUPPORTED_LENGTH = -2, /* prime factor > 5, or length > 2^24     */
+    FFT_ERR_OUT_OF_MEMORY = -3,      /* device or pinned allocation failed      */
+    FFT_ERR_ALIGNMENT = -4,          /* pointer not 8-byte aligned              */
+    FFT_ERR_OVERLAP = -5,            /* in and out partially overlap            */
+    FFT_ERR_HIP = -6,                /* a HIP runtime call failed               */
+    FFT_ERR_CALLBACK = -7,           /* a user fill/drain callback failed       */
+    FFT_ERR_BOUNDS = -8,             /* buffer smaller than the work needs      */
+    FFT_ERR_TIMEOUT = -9             /* a bounded device wait gave up           */
+} fft_status_t;
+
+typedef struct fftseg_plan *fft_plan_t;
+
+/* ------------------------------------------------------------------------
+ * Plain batched path (Sec. III: one batched plan over a block of segments).
+ * ------------------------------------------------------------------------ */
+
+/* Build a plan for `batch` segments of `segment_len` samples in direction
+ * FFT_FORWARD or FFT_INVERSE.  Factorises the length, picks the kernel (one
+ * LDS-resident pass up to 16384 samples, a two-pass "four-step" split
+ * N = N1*N2 above, a radix-by-radix fallback otherwise), uploads the
+ * twiddle tables (evaluated in FP64, rounded once to float32) and allocates
+ * the scratch of two-pass plans.  Returns NULL on error.  Validation:
+ * segment_len == 0, batch == 0, batch*segment_len*8 overflowing size_t or
+ * direction not +-1 -> FFT_ERR_INVALID_ARG; unsupported length ->
+ * FFT_ERR_UNSUPPORTED_LENGTH. */
+fft_plan_t fft_plan_create(size_t segment_len, size_t batch, int direction);
+
+/* Transform every segment: the record at byte offset s*segment_len*8 of
+ * `in` yields its spectrum at the same offset of `out`.  in == out (in
+ * place) is allowed; any other overlap gives FFT_ERR_OVERLAP.  Each buffer
+ * must lie inside one device allocation of at least batch*segment_len*8
+ * bytes from the pointer on (else FFT_ERR_BOUNDS). */
+int fft_exec_segments(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/* Same as fft_exec_segments for the first `batch` segments only
+ * (1 <= batch <= the plan's batch). */
+int fft_exec_segments_n(fft_plan_t plan, const void *in, void *out,
+                        size_t batch, void *stream);
+
+/* Synchronise the plan's last stream, then free the plan.  NULL is a no-op. */
+int fft_plan_destroy(fft_plan_t plan);
+
+/* Status and message of the calling thread's most recent call (FFT_OK and
+ * an empty message after a success). */
+int fft_last_status(void);
+const char *fft_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Introspection (host only, no device work).
+ * ------------------------------------------------------------------------ */
+
+/* Factorise n into the radices the planner would use for one pass of up to
+ * 16384 samples (or for the fallback path).  Writes up to `max` radices to
+ * `radices` and returns their count, or a negative fft_status_t. */
+int fft_plan_factorize(size_t n, int *radices, int max);
+
+/* Describe the plan as a JSON object (kind, kernels, radices, split,
+ * threads, LDS bytes, scratch bytes) into buf (NUL terminated, truncated to
+ * len).  Returns the full length needed, or a negative fft_status_t. */
+int fft_plan_describe(fft_plan_t plan, char *buf, size_t len);
+
+/* Bytes of device scratch the plan owns (0 for single-pass plans). */
+size_t fft_plan_scratch_bytes(fft_plan_t plan);
+
+/* ------------------------------------------------------------------------
+ * Streaming of signals larger than device memory (Sec. II-III: move data
+ * between host and device in few large transfers).
+ * ------------------------------------------------------------------------ */
+
+/* Producer: write chunk `chunk` (bytes = plan batch * segment_len * 8) into
+ * the library's pinned host slot `dst`.  Return 0 on success.  Called from
+ * the thread that called fft_exec_stream. */
+typedef int (*fft_fill_fn)(void *user, uint64_t chunk, void *dst, uint64_t bytes);
+/* Consumer: read the spectra of chunk `chunk` from pinned slot `src`. */
+typedef int (*fft_drain_fn)(void *user, uint64_t chunk, const void *src,
+                            uint64_t bytes);
+
+typedef struct {
+    double wall_s;          /* whole call                                  */
+    double fill_s;          /* time inside fill callbacks                  */
+    double drain_s;         /* time inside drain callbacks                 */
+    double h2d_s;           /* sum of host->device copy durations          */
+    double d2h_s;           /* sum of device->host copy durations          */
+    double compute_s;       /* sum of transform durations                  */
+    uint64_t bytes_h2d;
+    uint64_t bytes_d2h;
+    uint64_t chunks_done;   /* chunks fully drained                        */
+} fft_stream_stats_t;
+
+/* Transform n_chunks chunks of `batch` segments each (the plan's batch):
+ * chunk c is the signal's samples [c*batch*N, (c+1)*batch*N).  Pinned host
+ * ring of `n_slots` (>= 2) slots per direction; host->device copies run on
+ * one side stream, transforms on another, device->host copies on a third,
+ * ordered by events, so copies of chunk c+1 and c-1 overlap the transform
+ * of chunk c.  If a callback fails, the call stops, returns
+ * FFT_ERR_CALLBACK and stores the failing chunk index in *failed_chunk
+ * (chunks below it were fully drained: a caller may resume from there).
+ * drain may be NULL (results discarded).  stats may be NULL. */
+int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn fill,
+                    fft_drain_fn drain, void *user, int n_slots,
+                    uint64_t *failed_chunk, fft_stream_stats_t *stats);
+
+/* Same pipeline with caller-owned pinned buffers: chunk c is read from
+ * host_in[c % n_in] and its spectra written to host_out[c % n_out]; each
+ * must hold batch*segment_len*8 bytes of hipHostMalloc'd memory. */
+int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
+                           void *const *host_in, int n_in,
+                           void *const *host_out, int n_out, int n_slots,
+                           fft_stream_stats_t *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTSEG_H */

@@ -1,0 +1,281 @@
+"""Batched segment FFT on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libfftseg.so`` (C ABI in ``include/fftseg.h``):
+argument marshalling only -- every step of the transform runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams.
+
+The method (Tsiomenko & Rees, arXiv:1407.6915, Sec. III): a long signal is
+cut into fixed-length segments, each an <offset, FFT segment> record; one
+batched plan transforms all segments of a block, and each spectrum is kept
+at its record's offset.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import List, Optional
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfftseg.so")
+
+FORWARD = -1
+INVERSE = +1
+
+STATUS = {
+    0: "FFT_OK",
+    -1: "FFT_ERR_INVALID_ARG",
+    -2: "FFT_ERR_UNSUPPORTED_LENGTH",
+    -3: "FFT_ERR_OUT_OF_MEMORY",
+    -4: "FFT_ERR_ALIGNMENT",
+    -5: "FFT_ERR_OVERLAP",
+    -6: "FFT_ERR_HIP",
+    -7: "FFT_ERR_CALLBACK",
+    -8: "FFT_ERR_BOUNDS",
+    -9: "FFT_ERR_TIMEOUT",
+}
+
+
+class FFTError(RuntimeError):
+    """A library call failed; ``status`` is the fft_status_t value."""
+
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__("%s: %s" % (self.name, message))
+
+
+class StreamStats(ctypes.Structure):
+    """fft_stream_stats_t: wall/callback/copy/transform seconds and bytes."""
+    _fields_ = [("wall_s", ctypes.c_double), ("fill_s", ctypes.c_double),
+                ("drain_s", ctypes.c_double), ("h2d_s", ctypes.c_double),
+                ("d2h_s", ctypes.c_double), ("compute_s", ctypes.c_double),
+                ("bytes_h2d", ctypes.c_uint64), ("bytes_d2h", ctypes.c_uint64),
+                ("chunks_done", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
+                           ctypes.c_void_p, ctypes.c_uint64)
+DRAIN_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
+                            ctypes.c_void_p, ctypes.c_uint64)
+
+_lib = None
+
+
+def build() -> str:
+    """Compile libfftseg.so for gfx950 in-tree (hipcc)."""
+    from . import _build
+    global _lib
+    _lib = None
+    return _build.build()
+
+
+def _sig(lib, name, restype, argtypes):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+
+
+def lib():
+    """The loaded library (built first if no build exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint64
+    _sig(L, "fft_plan_create", vp, [sz, sz, i32])
+    _sig(L, "fft_plan_create_variant", vp, [sz, sz, i32, i32])
+    _sig(L, "fft_variant_count", i32, [sz])
+    _sig(L, "fft_exec_segments", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_exec_segments_n", i32, [vp, vp, vp, sz, vp])
+    _sig(L, "fft_plan_destroy", i32, [vp])
+    _sig(L, "fft_last_status", i32, [])
+    _sig(L, "fft_last_error", ctypes.c_char_p, [])
+    _sig(L, "fft_plan_factorize", i32, [sz, ctypes.POINTER(i32), i32])
+    _sig(L, "fft_plan_describe", i32, [vp, ctypes.c_char_p, sz])
+    _sig(L, "fft_plan_scratch_bytes", sz, [vp])
+    _sig(L, "fft_exec_stream", i32, [vp, u64, FILL_FN, DRAIN_FN, vp, i32,
+                                     ctypes.POINTER(u64), ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_exec_stream_pinned", i32, [vp, u64, ctypes.POINTER(vp), i32,
+                                            ctypes.POINTER(vp), i32, i32,
+                                            ctypes.POINTER(StreamStats)])
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().fft_last_error().decode(errors="replace")
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise FFTError(status, last_error())
+    return status
+
+
+def factorize(n: int) -> List[int]:
+    """Radices the planner uses for one pass of length n."""
+    buf = (ctypes.c_int * 32)()
+    k = _check(lib().fft_plan_factorize(n, buf, 32))
+    return [buf[i] for i in range(k)]
+
+
+def variant_count(n: int) -> int:
+    """Single-pass kernel variants compiled in for length n."""
+    return int(lib().fft_variant_count(n))
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_ptr(t, n_samples: int, name: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.dtype != torch.complex64:
+        raise TypeError("%s must be complex64 (got %s)" % (name, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be on a GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < n_samples:
+        raise ValueError("%s holds %d samples, %d needed" % (name, t.numel(), n_samples))
+    return t.data_ptr()
+
+
+class Plan:
+    """Plan for ``batch`` segments of ``segment_len`` complex64 samples.
+
+    ``exec(x, out)`` maps the record at byte offset s*N*8 of x to its
+    spectrum at the same offset of out (in place when out is x).
+    """
+
+    def __init__(self, segment_len: int, batch: int, direction: int = FORWARD,
+                 variant: Optional[int] = None):
+        L = lib()
+        if variant is None:
+            h = L.fft_plan_create(segment_len, batch, direction)
+        else:
+            h = L.fft_plan_create_variant(segment_len, batch, direction, variant)
+        if not h:
+            raise FFTError(L.fft_last_status(), last_error())
+        self._h = h
+        self.segment_len = segment_len
+        self.batch = batch
+        self.direction = direction
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("plan is destroyed")
+        return self._h
+
+    def exec_ptr(self, in_ptr: int, out_ptr: int, stream: int = 0,
+                 batch: Optional[int] = None) -> None:
+        """Raw device pointers (the C call, argument checks included)."""
+        if batch is None:
+            _check(lib().fft_exec_segments(self.handle, in_ptr, out_ptr, stream))
+        else:
+            _check(lib().fft_exec_segments_n(self.handle, in_ptr, out_ptr, batch,
+                                             stream))
+
+    def exec(self, x, out=None, stream=None, batch: Optional[int] = None):
+        """Transform torch complex64 GPU tensors; returns ``out``."""
+        import torch
+        b = self.batch if batch is None else batch
+        n = b * self.segment_len
+        ip = _tensor_ptr(x, n, "x")
+        if out is None:
+            out = torch.empty(n, dtype=torch.complex64, device=x.device)
+        op = _tensor_ptr(out, n, "out")
+        self.exec_ptr(ip, op, _stream_handle(stream), batch)
+        return out
+
+    def exec_stream(self, n_chunks: int, fill, drain=None, n_slots: int = 3):
+        """Stream n_chunks chunks of this plan's batch through the GPU.
+
+        ``fill``/``drain`` are either Python callables ``f(chunk, ptr,
+        nbytes) -> int`` (0 = success) working on the library's pinned slot
+        at host address ptr, or ``(address, user)`` pairs naming a native C
+        callback and the object whose address it receives.  Returns
+        (status, failed_chunk or None, stats dict); a callback failure is
+        reported in the status, not raised.
+        """
+        user = None
+        keep = []
+
+        def wrap(cb, ftype):
+            nonlocal user
+            if cb is None:
+                return ftype()
+            if isinstance(cb, tuple):
+                addr, obj = cb
+                if user is not None and obj is not user:
+                    raise ValueError("native fill and drain must share one user object")
+                user = obj
+                return ftype(addr)
+            f = ftype(lambda _u, c, ptr, nb: int(cb(int(c), ptr, int(nb))))
+            keep.append(f)
+            return f
+
+        f_fill = wrap(fill, FILL_FN)
+        f_drain = wrap(drain, DRAIN_FN)
+        uptr = ctypes.cast(ctypes.pointer(user), ctypes.c_void_p) if user is not None else None
+        failed = ctypes.c_uint64(0)
+        st = StreamStats()
+        rc = lib().fft_exec_stream(self.handle, n_chunks, f_fill, f_drain, uptr,
+                                   n_slots, ctypes.byref(failed), ctypes.byref(st))
+        if rc < 0 and rc != -7:
+            raise FFTError(rc, last_error())
+        fc = None if failed.value == 2 ** 64 - 1 else int(failed.value)
+        return rc, fc, st.as_dict()
+
+    def exec_stream_pinned(self, n_chunks: int, host_in, host_out, n_slots: int = 3):
+        """Stream through caller-owned pinned host buffers (lists of host
+        addresses): chunk c reads host_in[c % len] and writes host_out[c % len]."""
+        vin = (ctypes.c_void_p * len(host_in))(*host_in)
+        vout = (ctypes.c_void_p * len(host_out))(*host_out)
+        st = StreamStats()
+        _check(lib().fft_exec_stream_pinned(self.handle, n_chunks, vin, len(host_in),
+                                            vout, len(host_out), n_slots,
+                                            ctypes.byref(st)))
+        return st.as_dict()
+
+    def describe(self) -> dict:
+        L = lib()
+        need = _check(L.fft_plan_describe(self.handle, None, 0))
+        buf = ctypes.create_string_buffer(need + 1)
+        _check(L.fft_plan_describe(self.handle, buf, need + 1))
+        return json.loads(buf.value.decode())
+
+    @property
+    def scratch_bytes(self) -> int:
+        return int(lib().fft_plan_scratch_bytes(self.handle))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

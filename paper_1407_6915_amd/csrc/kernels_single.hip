@@ -1,0 +1,96 @@
+// Single-pass (LDS-resident) kernel variants per segment length.
+//
+// Variant 0 of each length is the planner's default; the others are the
+// autotuner's candidates (different radix orders, threads per segment,
+// segments per workgroup and LDS padding).
+#include "registry.hpp"
+#include "tile.hpp"
+
+namespace fftseg {
+namespace {
+
+template <int N, int T, int S, int PS, int... Rs>
+struct SpInst {
+    using Sh = Shape<N, T, Radices<Rs...>>;
+    using Pol = SinglePassPolicy<Sh, S, PS>;
+
+    static void launch(int dir, const void *in, void *out, const void *tw,
+                       uint64_t batch, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((single_pass_kernel<Sh, Pol, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch);
+        else
+            hipLaunchKernelGGL((single_pass_kernel<Sh, Pol, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch);
+    }
+    static SinglePassDesc desc(int variant)
+    {
+        SinglePassDesc d{};
+        d.n = N;
+        d.variant = variant;
+        d.threads = T;
+        d.segs_per_wg = S;
+        d.pad_shift = PS;
+        d.lds_bytes = Pol::kLdsElems * (int)sizeof(c32);
+        d.nrad = (int)sizeof...(Rs);
+        const int r[] = {Rs...};
+        for (int i = 0; i < d.nrad; ++i)
+            d.radices[i] = r[i];
+        d.launch = &launch;
+        d.kernel[0] = (const void *)&single_pass_kernel<Sh, Pol, -1>;
+        d.kernel[1] = (const void *)&single_pass_kernel<Sh, Pol, 1>;
+        return d;
+    }
+};
+
+//                 N      T    S  PS  radices                       variant
+const SinglePassDesc kTable[] = {
+    SpInst<2, 1, 64, 0, 2>::desc(0),
+    SpInst<4, 1, 64, 0, 4>::desc(0),
+    SpInst<8, 1, 64, 0, 8>::desc(0),
+    SpInst<16, 1, 64, 0, 16>::desc(0),
+    SpInst<32, 4, 32, 4, 8, 4>::desc(0),
+    SpInst<64, 8, 32, 4, 8, 8>::desc(0),
+    SpInst<128, 8, 32, 4, 16, 8>::desc(0),
+    SpInst<256, 16, 16, 4, 16, 16>::desc(0),
+    SpInst<256, 16, 8, 4, 16, 16>::desc(1),
+    SpInst<512, 64, 4, 4, 8, 8, 8>::desc(0),
+    SpInst<512, 32, 8, 4, 16, 16, 2>::desc(1),
+    SpInst<1024, 64, 4, 4, 16, 16, 4>::desc(0),
+    SpInst<1024, 64, 4, 4, 4, 16, 16>::desc(1),
+    SpInst<1024, 128, 2, 4, 8, 8, 16>::desc(2),
+    SpInst<1024, 64, 2, 4, 16, 16, 4>::desc(3),
+    SpInst<2048, 128, 2, 4, 16, 16, 8>::desc(0),
+    SpInst<2048, 128, 1, 4, 16, 16, 8>::desc(1),
+    SpInst<4096, 256, 1, 4, 16, 16, 16>::desc(0),
+    SpInst<4096, 256, 1, 0, 16, 16, 16>::desc(1),
+    SpInst<4096, 512, 1, 4, 8, 8, 8, 8>::desc(2),
+    SpInst<4096, 128, 2, 4, 16, 16, 16>::desc(3),
+    SpInst<4096, 256, 1, 5, 16, 16, 16>::desc(4),
+    SpInst<8192, 512, 1, 4, 16, 16, 16, 2>::desc(0),
+    SpInst<8192, 256, 1, 4, 32, 16, 16>::desc(1),
+    SpInst<16384, 1024, 1, 4, 16, 16, 16, 4>::desc(0),
+    SpInst<16384, 512, 1, 4, 16, 16, 16, 4>::desc(1),
+    // mixed radix 2/3/5
+    SpInst<1000, 100, 2, 4, 10, 10, 10>::desc(0),
+    SpInst<1000, 125, 2, 4, 8, 5, 5, 5>::desc(1),
+    SpInst<1000, 200, 1, 4, 5, 5, 5, 8>::desc(2),
+    SpInst<1536, 96, 2, 4, 16, 16, 6>::desc(0),
+    SpInst<1536, 128, 2, 4, 12, 8, 16>::desc(1),
+    SpInst<1536, 192, 1, 4, 8, 8, 8, 3>::desc(2),
+    SpInst<6000, 400, 1, 4, 16, 15, 25>::desc(0),
+    SpInst<6000, 200, 1, 4, 10, 10, 10, 6>::desc(1),
+    SpInst<6000, 300, 1, 4, 20, 20, 15>::desc(2),
+};
+
+}  // namespace
+
+const SinglePassDesc *single_pass_table(int *count)
+{
+    *count = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace fftseg

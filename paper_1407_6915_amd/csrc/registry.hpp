@@ -1,0 +1,59 @@
+// Compiled kernel variants and their launch shapes, as seen by the planner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftseg {
+
+constexpr int kMaxRadices = 12;
+
+using sp_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
+                              uint64_t batch, unsigned grid, hipStream_t s);
+using col_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
+                               const void *tl, const void *th, int sh, int n2,
+                               uint64_t batch, unsigned grid, hipStream_t s);
+using row_launch_fn = void (*)(int dir, const void *ybuf, void *out, const void *tw,
+                               int n1, uint64_t batch, unsigned grid, hipStream_t s);
+
+// One LDS-resident pass over whole segments.
+struct SinglePassDesc {
+    int n;              // segment length
+    int variant;        // 0 = default for this length
+    int threads;        // threads per segment (T)
+    int segs_per_wg;    // segments per workgroup (S)
+    int pad_shift;      // one LDS pad element every 2^pad_shift (0: none)
+    int lds_bytes;
+    int nrad;
+    int radices[kMaxRadices];
+    sp_launch_fn launch;
+    const void *kernel[2];  // [0] forward, [1] inverse (occupancy queries)
+};
+
+// Four-step pass A: N1-point column transforms, C columns per workgroup.
+struct ColumnDesc {
+    int n1, cols, threads, lds_bytes, nrad;
+    int radices[kMaxRadices];
+    col_launch_fn launch;
+    const void *kernel[2];
+};
+
+// Four-step pass B: N2-point row transforms, C rows per workgroup.
+struct RowDesc {
+    int n2, rows, threads, lds_bytes, nrad;
+    int radices[kMaxRadices];
+    row_launch_fn launch;
+    const void *kernel[2];
+};
+
+const SinglePassDesc *single_pass_table(int *count);
+const ColumnDesc *column_table(int *count);
+const RowDesc *row_table(int *count);
+
+// Fallback radix stage over global memory (radix in {2,3,4,5,8,16}).
+bool generic_radix_supported(int radix);
+void launch_generic_stage(int radix, int dir, const void *in, void *out,
+                          const void *tl, const void *th, int sh, uint64_t n,
+                          uint64_t l, uint64_t batch, unsigned grid, hipStream_t s);
+
+}  // namespace fftseg

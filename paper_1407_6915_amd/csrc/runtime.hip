@@ -1,0 +1,708 @@
+// Planner, twiddle tables, argument checks and the C entry points of the
+// batched segment FFT (declared in fftseg.h).
+#include "fftseg.h"
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace fftseg {
+
+// ---------------------------------------------------------------------------
+// per-thread status
+namespace {
+thread_local int t_status = FFT_OK;
+thread_local char t_msg[512] = "";
+}  // namespace
+
+int set_ok()
+{
+    t_status = FFT_OK;
+    t_msg[0] = 0;
+    return FFT_OK;
+}
+
+int set_error(int status, const char *fmt, ...)
+{
+    t_status = status;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_msg, sizeof(t_msg), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    return set_error(FFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int last_status() { return t_status; }
+const char *last_message() { return t_msg; }
+
+// ---------------------------------------------------------------------------
+// twiddles: exp(-2 pi i m / n) in FP64 with the angle folded to the first
+// octant in exact integer arithmetic, rounded once to float32
+c32 root_forward(uint64_t m, uint64_t n)
+{
+    m %= n;
+    // angle 2 pi m / n = (pi/4) (o + r/n) with 8m = o*n + r; quadrant
+    // j = floor((o + 1) / 2) and x = (pi/4) (o - 2j + r/n) in [-pi/4, pi/4)
+    const unsigned __int128 m8 = (unsigned __int128)m * 8u;
+    const uint64_t o = (uint64_t)(m8 / n);
+    const uint64_t r = (uint64_t)(m8 - (unsigned __int128)o * n);
+    const uint64_t j = (o + 1) / 2;
+    const double quarter_pi = 0.78539816339744830961566084581987572;
+    const double x = ((double)((long long)o - 2 * (long long)j) + (double)r / (double)n) *
+                     quarter_pi;
+    const double cx = std::cos(x), sx = std::sin(x);
+    double c, s;
+    switch (j & 3) {
+    case 0: c = cx; s = sx; break;
+    case 1: c = -sx; s = cx; break;
+    case 2: c = -cx; s = -sx; break;
+    default: c = sx; s = -cx; break;
+    }
+    return c32{(float)c, (float)(-s)};
+}
+
+namespace {
+
+std::vector<c32> root_table(uint64_t n)
+{
+    std::vector<c32> t(n);
+    for (uint64_t m = 0; m < n; ++m)
+        t[m] = root_forward(m, n);
+    return t;
+}
+
+int ilog2_ceil(uint64_t v)
+{
+    int k = 0;
+    while ((1ull << k) < v)
+        ++k;
+    return k;
+}
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+bool smooth235(uint64_t n)
+{
+    if (n == 0)
+        return false;
+    for (uint64_t p : {2ull, 3ull, 5ull})
+        while (n % p == 0)
+            n /= p;
+    return n == 1;
+}
+
+// greedy radix list for the global-memory fallback
+std::vector<int> generic_radices(uint64_t n)
+{
+    std::vector<int> r;
+    for (int p : {16, 8, 4, 2, 5, 3}) {
+        while (n % p == 0 && n > 1) {
+            r.push_back(p);
+            n /= p;
+        }
+    }
+    return r;
+}
+
+hipError_t upload(const std::vector<c32> &h, void **d)
+{
+    *d = nullptr;
+    hipError_t e = hipMalloc(d, h.size() * sizeof(c32));
+    if (e != hipSuccess) {
+        *d = nullptr;
+        return e;
+    }
+    e = hipMemcpy(*d, h.data(), h.size() * sizeof(c32), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(*d);
+        *d = nullptr;
+    }
+    return e;
+}
+
+// the tuning table: preferred single-pass variant per length
+std::mutex g_tune_mu;
+std::vector<std::pair<uint64_t, int>> g_tuned;
+
+}  // namespace
+
+int tuned_variant(uint64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.first == n)
+            return p.second;
+    return -1;
+}
+
+void set_tuned_variant(uint64_t n, int variant)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.first == n) {
+            p.second = variant;
+            return;
+        }
+    g_tuned.emplace_back(n, variant);
+}
+
+void clear_tuned()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+std::vector<std::pair<uint64_t, int>> tuned_snapshot()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tuned;
+}
+
+const SinglePassDesc *find_single(uint64_t n, int variant)
+{
+    int cnt = 0;
+    const SinglePassDesc *t = single_pass_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if ((uint64_t)t[i].n == n && t[i].variant == variant)
+            return &t[i];
+    return nullptr;
+}
+
+int variant_count(uint64_t n)
+{
+    int cnt = 0, k = 0;
+    const SinglePassDesc *t = single_pass_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        k += (uint64_t)t[i].n == n;
+    return k;
+}
+
+// best four-step split n = n1 * n2 with compiled column and row tiles
+bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row)
+{
+    int nc = 0, nr = 0;
+    const ColumnDesc *ct = column_table(&nc);
+    const RowDesc *rt = row_table(&nr);
+    double best = 1e30;
+    *col = nullptr;
+    *row = nullptr;
+    for (int i = 0; i < nc; ++i) {
+        if (n % (uint64_t)ct[i].n1)
+            continue;
+        const uint64_t n2 = n / (uint64_t)ct[i].n1;
+        for (int j = 0; j < nr; ++j) {
+            if ((uint64_t)rt[j].n2 != n2)
+                continue;
+            if (n2 % (uint64_t)ct[i].cols || (uint64_t)ct[i].n1 % (uint64_t)rt[j].rows)
+                continue;
+            // prefer balanced splits, then the smaller column length
+            const double score =
+                std::fabs(std::log2((double)ct[i].n1) - std::log2((double)n2)) * 2.0 +
+                (ct[i].n1 > (int)n2 ? 1.0 : 0.0);
+            if (score < best) {
+                best = score;
+                *col = &ct[i];
+                *row = &rt[j];
+            }
+        }
+    }
+    return *col != nullptr;
+}
+
+static int device_cus(int dev)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return 256;
+    return p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+}
+
+unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
+                  int grid_mult)
+{
+    uint64_t g = work_groups;
+    if (grid_mult > 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
+                hipSuccess ||
+            per_cu <= 0) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        const uint64_t cap = (uint64_t)per_cu * (uint64_t)device_cus(dev) * (uint64_t)grid_mult;
+        g = std::min<uint64_t>(g, cap);
+    }
+    g = std::min<uint64_t>(g, 0x7fffffffull);
+    return (unsigned)std::max<uint64_t>(g, 1);
+}
+
+int env_grid_mult()
+{
+    const char *e = getenv("FFTSEG_GRID_MULT");
+    return e ? atoi(e) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// plan construction
+int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant)
+{
+    p->n = n;
+    p->batch = batch;
+    p->dir = dir;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_HIP, "no HIP device available");
+    }
+    p->grid_mult = env_grid_mult();
+    hipError_t e;
+    if (n == 1) {
+        p->kind = Plan::COPY;
+        return set_ok();
+    }
+    int variant = forced_variant >= 0 ? forced_variant : tuned_variant(n);
+    if (variant < 0)
+        variant = 0;
+    p->sp = find_single(n, variant);
+    if (!p->sp && forced_variant < 0)
+        p->sp = find_single(n, 0);
+    if (forced_variant >= 0 && !p->sp)
+        return set_error(FFT_ERR_INVALID_ARG, "length %llu has no variant %d",
+                         (unsigned long long)n, forced_variant);
+    if (p->sp) {
+        p->kind = Plan::SINGLE;
+        if ((e = upload(root_table(n), &p->tw)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+        return set_ok();
+    }
+    const uint64_t max_sub_samples = 1ull << 29;  // 4 GiB of complex64 per scratch buffer
+    p->sh = ilog2_ceil(n) / 2 + (ilog2_ceil(n) & 1);
+    {
+        const uint64_t lo = 1ull << p->sh;
+        std::vector<c32> tl(lo), th((n + lo - 1) / lo);
+        for (uint64_t j = 0; j < lo; ++j)
+            tl[j] = root_forward(j, n);
+        for (uint64_t j = 0; j < th.size(); ++j)
+            th[j] = root_forward(j * lo, n);
+        if ((e = upload(tl, &p->tl)) != hipSuccess || (e = upload(th, &p->th)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+    }
+    p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / n));
+    if (find_split(n, &p->col, &p->row)) {
+        p->kind = Plan::FOURSTEP;
+        p->n1 = (uint64_t)p->col->n1;
+        p->n2 = (uint64_t)p->row->n2;
+        if ((e = upload(root_table(p->n1), &p->tw)) != hipSuccess ||
+            (e = upload(root_table(p->n2), &p->tw2)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+        p->scratch_bytes = p->sub_batch * n * sizeof(c32);
+    } else {
+        p->kind = Plan::GENERIC;
+        p->radices = generic_radices(n);
+        p->scratch_bytes = 2 * p->sub_batch * n * sizeof(c32);
+    }
+    e = hipMalloc(&p->scratch, p->scratch_bytes);
+    if (e != hipSuccess) {
+        p->scratch = nullptr;
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "scratch of %zu bytes", p->scratch_bytes);
+    }
+    return set_ok();
+}
+
+void plan_free(Plan *p)
+{
+    if (p->used && p->last_stream_valid)
+        (void)hipStreamSynchronize(p->last_stream);
+    for (void *q : {p->tw, p->tw2, p->tl, p->th, p->scratch})
+        if (q)
+            (void)hipFree(q);
+    stream_state_free(p);
+    if (p->graph_exec)
+        (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    p->tw = p->tw2 = p->tl = p->th = p->scratch = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks before any device work
+int check_device_range(const void *ptr, uint64_t bytes, const char *name)
+{
+    void *base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, const_cast<void *>(ptr));
+    if (e == hipSuccess && base) {
+        const uintptr_t b = (uintptr_t)base, q = (uintptr_t)ptr;
+        if (q < b || q - b > size || bytes > size - (q - b))
+            return set_error(FFT_ERR_BOUNDS,
+                             "%s: %llu bytes from %p exceed its allocation [%p, +%zu)", name,
+                             (unsigned long long)bytes, ptr, base, size);
+        return FFT_OK;
+    }
+    (void)hipGetLastError();
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_INVALID_ARG, "%s (%p) is not device memory", name, ptr);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return set_error(FFT_ERR_INVALID_ARG, "%s (%p) is not device memory", name, ptr);
+    return FFT_OK;
+}
+
+int check_io(const void *in, const void *out, uint64_t bytes)
+{
+    if (!in || !out)
+        return set_error(FFT_ERR_INVALID_ARG, "in/out must not be NULL");
+    if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
+        return set_error(FFT_ERR_ALIGNMENT, "in/out must be 8-byte aligned");
+    if (in != out) {
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        if (a < b + bytes && b < a + bytes)
+            return set_error(FFT_ERR_OVERLAP, "in and out overlap without being equal");
+    }
+    int st = check_device_range(in, bytes, "in");
+    if (st != FFT_OK)
+        return st;
+    if (in != out && (st = check_device_range(out, bytes, "out")) != FFT_OK)
+        return st;
+    return FFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// enqueue the transform of `batch` segments (arguments already checked)
+int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s)
+{
+    const uint64_t n = p->n;
+    const int dir = p->dir;
+    switch (p->kind) {
+    case Plan::COPY:
+        if (in != out) {
+            hipError_t e = hipMemcpyAsync(out, in, batch * sizeof(c32),
+                                          hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess)
+                return hip_error(e, "identity copy");
+        }
+        break;
+    case Plan::SINGLE: {
+        const SinglePassDesc *d = p->sp;
+        const uint64_t groups = (batch + d->segs_per_wg - 1) / d->segs_per_wg;
+        const unsigned grid = grid_for(d->kernel[dir > 0], d->threads * d->segs_per_wg,
+                                       groups, p->device, p->grid_mult);
+        d->launch(dir, in, out, p->tw, batch, grid, s);
+        break;
+    }
+    case Plan::FOURSTEP: {
+        const ColumnDesc *cd = p->col;
+        const RowDesc *rd = p->row;
+        for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch) {
+            const uint64_t sb = std::min(p->sub_batch, batch - s0);
+            const c32 *x = (const c32 *)in + s0 * n;
+            c32 *y = (c32 *)out + s0 * n;
+            const uint64_t ta = sb * (p->n2 / (uint64_t)cd->cols);
+            const uint64_t tb = sb * (p->n1 / (uint64_t)rd->rows);
+            const unsigned ga = grid_for(cd->kernel[dir > 0], cd->threads * cd->cols, ta,
+                                         p->device, p->grid_mult);
+            const unsigned gb = grid_for(rd->kernel[dir > 0], rd->threads * rd->rows, tb,
+                                         p->device, p->grid_mult);
+            cd->launch(dir, x, p->scratch, p->tw, p->tl, p->th, p->sh, (int)p->n2, sb, ga, s);
+            rd->launch(dir, p->scratch, y, p->tw2, (int)p->n1, sb, gb, s);
+        }
+        break;
+    }
+    case Plan::GENERIC: {
+        const int ns = (int)p->radices.size();
+        c32 *bufs[2] = {(c32 *)p->scratch, (c32 *)p->scratch + p->sub_batch * n};
+        for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch) {
+            const uint64_t sb = std::min(p->sub_batch, batch - s0);
+            const c32 *x = (const c32 *)in + s0 * n;
+            c32 *y = (c32 *)out + s0 * n;
+            const uint64_t threads_total = sb * n;
+            uint64_t l = 1;
+            for (int i = 0; i < ns; ++i) {
+                const int r = p->radices[i];
+                const void *src = i == 0 ? (const void *)x : (const void *)bufs[(i - 1) & 1];
+                void *dst = (i == ns - 1 && !(ns == 1 && in == out)) ? (void *)y
+                                                                     : (void *)bufs[i & 1];
+                const uint64_t work = threads_total / r;
+                const unsigned grid =
+                    (unsigned)std::min<uint64_t>((work + 255) / 256, 1ull << 20);
+                launch_generic_stage(r, dir, src, dst, p->tl, p->th, p->sh, n, l, sb, grid, s);
+                l *= (uint64_t)r;
+            }
+            if (ns == 1 && in == out) {
+                hipError_t e = hipMemcpyAsync(y, bufs[0], sb * n * sizeof(c32),
+                                              hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess)
+                    return hip_error(e, "fallback copy");
+            }
+        }
+        break;
+    }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_error(e, "kernel launch");
+    p->used = true;
+    p->last_stream = s;
+    p->last_stream_valid = true;
+    return set_ok();
+}
+
+int plan_describe(const Plan *p, std::string &js)
+{
+    char buf[1024];
+    auto rad = [](const int *r, int n) {
+        std::string s = "[";
+        for (int i = 0; i < n; ++i)
+            s += (i ? "," : "") + std::to_string(r[i]);
+        return s + "]";
+    };
+    switch (p->kind) {
+    case Plan::COPY:
+        snprintf(buf, sizeof buf, "{\"kind\":\"copy\",\"n\":%llu,\"batch\":%llu}",
+                 (unsigned long long)p->n, (unsigned long long)p->batch);
+        break;
+    case Plan::SINGLE:
+        snprintf(buf, sizeof buf,
+                 "{\"kind\":\"single_pass\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
+                 "\"variant\":%d,\"radices\":%s,\"threads_per_segment\":%d,"
+                 "\"segments_per_workgroup\":%d,\"lds_pad_shift\":%d,\"lds_bytes\":%d,"
+                 "\"scratch_bytes\":0}",
+                 (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
+                 p->sp->variant, rad(p->sp->radices, p->sp->nrad).c_str(), p->sp->threads,
+                 p->sp->segs_per_wg, p->sp->pad_shift, p->sp->lds_bytes);
+        break;
+    case Plan::FOURSTEP:
+        snprintf(buf, sizeof buf,
+                 "{\"kind\":\"four_step\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
+                 "\"n1\":%llu,\"n2\":%llu,\"radices_n1\":%s,\"radices_n2\":%s,"
+                 "\"columns_per_workgroup\":%d,\"rows_per_workgroup\":%d,"
+                 "\"lds_bytes\":[%d,%d],\"sub_batch\":%llu,\"scratch_bytes\":%zu}",
+                 (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
+                 (unsigned long long)p->n1, (unsigned long long)p->n2,
+                 rad(p->col->radices, p->col->nrad).c_str(),
+                 rad(p->row->radices, p->row->nrad).c_str(), p->col->cols, p->row->rows,
+                 p->col->lds_bytes, p->row->lds_bytes, (unsigned long long)p->sub_batch,
+                 p->scratch_bytes);
+        break;
+    case Plan::GENERIC:
+        snprintf(buf, sizeof buf,
+                 "{\"kind\":\"radix_stages\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
+                 "\"radices\":%s,\"sub_batch\":%llu,\"scratch_bytes\":%zu}",
+                 (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
+                 rad(p->radices.data(), (int)p->radices.size()).c_str(),
+                 (unsigned long long)p->sub_batch, p->scratch_bytes);
+        break;
+    }
+    js = buf;
+    return FFT_OK;
+}
+
+int validate_create(uint64_t n, uint64_t batch, int dir)
+{
+    if (n == 0)
+        return set_error(FFT_ERR_INVALID_ARG, "segment_len must be > 0");
+    if (batch == 0)
+        return set_error(FFT_ERR_INVALID_ARG, "batch must be > 0");
+    if (dir != FFT_FORWARD && dir != FFT_INVERSE)
+        return set_error(FFT_ERR_INVALID_ARG, "direction must be -1 or +1 (got %d)", dir);
+    if (n > (1ull << 24))
+        return set_error(FFT_ERR_UNSUPPORTED_LENGTH, "segment_len %llu exceeds 2^24",
+                         (unsigned long long)n);
+    if (!smooth235(n))
+        return set_error(FFT_ERR_UNSUPPORTED_LENGTH,
+                         "segment_len %llu has a prime factor other than 2, 3, 5",
+                         (unsigned long long)n);
+    if (batch > SIZE_MAX / 8 / n)
+        return set_error(FFT_ERR_INVALID_ARG, "batch * segment_len * 8 overflows size_t");
+    return FFT_OK;
+}
+
+int factorize(uint64_t n, int *radices, int max)
+{
+    if (n == 0)
+        return set_error(FFT_ERR_INVALID_ARG, "n must be > 0");
+    if (n > (1ull << 24) || !smooth235(n))
+        return set_error(FFT_ERR_UNSUPPORTED_LENGTH, "unsupported length %llu",
+                         (unsigned long long)n);
+    std::vector<int> r;
+    int v = tuned_variant(n);
+    const SinglePassDesc *d = find_single(n, v < 0 ? 0 : v);
+    if (!d)
+        d = find_single(n, 0);
+    if (d)
+        r.assign(d->radices, d->radices + d->nrad);
+    else
+        r = generic_radices(n);
+    if (!radices && max != 0)
+        return set_error(FFT_ERR_INVALID_ARG, "radices is NULL");
+    for (int i = 0; i < (int)r.size() && i < max; ++i)
+        radices[i] = r[i];
+    set_ok();
+    return (int)r.size();
+}
+
+}  // namespace fftseg
+
+// ===========================================================================
+// C entry points
+using namespace fftseg;
+
+#define FFT_GUARD_BEGIN try {
+#define FFT_GUARD_END(ret)                                                         \
+    }                                                                              \
+    catch (const std::bad_alloc &)                                                 \
+    {                                                                              \
+        set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");                \
+        return ret;                                                                \
+    }                                                                              \
+    catch (...)                                                                    \
+    {                                                                              \
+        set_error(FFT_ERR_INVALID_ARG, "internal error");                          \
+        return ret;                                                                \
+    }
+
+static fft_plan_t create_impl(size_t segment_len, size_t batch, int direction, int variant)
+{
+    if (validate_create(segment_len, batch, direction) != FFT_OK)
+        return nullptr;
+    Plan *p = new Plan();
+    if (plan_build(p, segment_len, batch, direction, variant) != FFT_OK) {
+        const int st = last_status();
+        std::string msg = last_message();
+        plan_free(p);
+        delete p;
+        set_error(st, "%s", msg.c_str());
+        return nullptr;
+    }
+    return reinterpret_cast<fft_plan_t>(p);
+}
+
+extern "C" fft_plan_t fft_plan_create(size_t segment_len, size_t batch, int direction)
+{
+    FFT_GUARD_BEGIN
+    return create_impl(segment_len, batch, direction, -1);
+    FFT_GUARD_END(nullptr)
+}
+
+extern "C" fft_plan_t fft_plan_create_variant(size_t segment_len, size_t batch,
+                                              int direction, int variant)
+{
+    FFT_GUARD_BEGIN
+    if (variant < 0) {
+        set_error(FFT_ERR_INVALID_ARG, "variant must be >= 0");
+        return nullptr;
+    }
+    return create_impl(segment_len, batch, direction, variant);
+    FFT_GUARD_END(nullptr)
+}
+
+extern "C" int fft_variant_count(size_t n)
+{
+    set_ok();
+    return variant_count(n);
+}
+
+extern "C" int fft_exec_segments_n(fft_plan_t plan, const void *in, void *out,
+                                   size_t batch, void *stream)
+{
+    FFT_GUARD_BEGIN
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p)
+        return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+    if (batch == 0 || batch > p->batch)
+        return set_error(FFT_ERR_INVALID_ARG, "batch %zu outside [1, %llu]", batch,
+                         (unsigned long long)p->batch);
+    const uint64_t bytes = (uint64_t)batch * p->n * sizeof(c32);
+    int st = check_io(in, out, bytes);
+    if (st != FFT_OK)
+        return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return hip_error(hipGetLastError(), "hipGetDevice");
+    if (cur != p->device && hipSetDevice(p->device) != hipSuccess)
+        return hip_error(hipGetLastError(), "hipSetDevice");
+    st = plan_enqueue(p, in, out, batch, (hipStream_t)stream);
+    if (cur != p->device)
+        (void)hipSetDevice(cur);
+    return st;
+    FFT_GUARD_END(FFT_ERR_INVALID_ARG)
+}
+
+extern "C" int fft_exec_segments(fft_plan_t plan, const void *in, void *out, void *stream)
+{
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p)
+        return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+    return fft_exec_segments_n(plan, in, out, p->batch, stream);
+}
+
+extern "C" int fft_plan_destroy(fft_plan_t plan)
+{
+    FFT_GUARD_BEGIN
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p)
+        return set_ok();
+    plan_free(p);
+    delete p;
+    return set_ok();
+    FFT_GUARD_END(FFT_ERR_INVALID_ARG)
+}
+
+extern "C" int fft_last_status(void) { return last_status(); }
+extern "C" const char *fft_last_error(void) { return last_message(); }
+
+extern "C" int fft_plan_factorize(size_t n, int *radices, int max)
+{
+    FFT_GUARD_BEGIN
+    return factorize(n, radices, max);
+    FFT_GUARD_END(FFT_ERR_INVALID_ARG)
+}
+
+extern "C" int fft_plan_describe(fft_plan_t plan, char *buf, size_t len)
+{
+    FFT_GUARD_BEGIN
+    const Plan *p = reinterpret_cast<const Plan *>(plan);
+    if (!p)
+        return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+    std::string js;
+    plan_describe(p, js);
+    if (buf && len) {
+        const size_t k = std::min(len - 1, js.size());
+        std::memcpy(buf, js.data(), k);
+        buf[k] = 0;
+    }
+    set_ok();
+    return (int)js.size();
+    FFT_GUARD_END(FFT_ERR_INVALID_ARG)
+}
+
+extern "C" size_t fft_plan_scratch_bytes(fft_plan_t plan)
+{
+    const Plan *p = reinterpret_cast<const Plan *>(plan);
+    if (!p) {
+        set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+        return 0;
+    }
+    set_ok();
+    return p->scratch_bytes;
+}

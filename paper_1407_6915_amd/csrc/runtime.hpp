@@ -1,0 +1,74 @@
+// Internal runtime declarations shared by the entry-point sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "radix.hpp"
+#include "registry.hpp"
+
+namespace fftseg {
+
+struct Plan {
+    enum Kind { COPY, SINGLE, FOURSTEP, GENERIC };
+    uint64_t n = 0, batch = 0;
+    int dir = -1;
+    int device = 0;
+    Kind kind = COPY;
+    const SinglePassDesc *sp = nullptr;
+    const ColumnDesc *col = nullptr;
+    const RowDesc *row = nullptr;
+    uint64_t n1 = 0, n2 = 0;
+    std::vector<int> radices;   // fallback path
+    void *tw = nullptr;         // W_N (single pass) or W_N1 (four-step) table
+    void *tw2 = nullptr;        // W_N2 table (four-step)
+    void *tl = nullptr, *th = nullptr;  // two-level W_N table
+    int sh = 0;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    uint64_t sub_batch = 0;
+    int grid_mult = 0;          // 0: one workgroup per tile
+    bool used = false;
+    bool last_stream_valid = false;
+    hipStream_t last_stream = nullptr;
+    // graph replay state
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_in = nullptr;
+    void *graph_out = nullptr;
+    void *stream_state = nullptr;  // pinned host ring of the streaming path
+};
+
+int set_ok();
+int set_error(int status, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+int last_status();
+const char *last_message();
+
+c32 root_forward(uint64_t m, uint64_t n);
+const SinglePassDesc *find_single(uint64_t n, int variant);
+int variant_count(uint64_t n);
+bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row);
+unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
+                  int grid_mult);
+
+int validate_create(uint64_t n, uint64_t batch, int dir);
+int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant);
+void plan_free(Plan *p);
+int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
+int plan_describe(const Plan *p, std::string &js);
+int check_io(const void *in, const void *out, uint64_t bytes);
+int check_device_range(const void *ptr, uint64_t bytes, const char *name);
+
+void stream_state_free(Plan *p);
+
+int tuned_variant(uint64_t n);
+void set_tuned_variant(uint64_t n, int variant);
+void clear_tuned();
+std::vector<std::pair<uint64_t, int>> tuned_snapshot();
+
+}  // namespace fftseg

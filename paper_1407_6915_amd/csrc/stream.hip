@@ -1,0 +1,365 @@
+// Streaming of signals larger than device memory (fft_exec_stream*).
+//
+// The paper moves each block of segments to the GPU in one large transfer
+// because the host link is slow next to device memory (Sec. II-III).  Here
+// chunk c of `batch` segments goes host -> device on one stream, is
+// transformed in place on a second and comes back on a third; events order
+// the three, so the copies of chunks c+1 and c-1 overlap the transform of
+// chunk c.  Host slots live in pinned memory allocated with hipHostMalloc.
+#include "fftseg.h"
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+namespace fftseg {
+namespace {
+
+constexpr int kDevSlots = 3;  // device buffers: copy-in, transform, copy-out
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ChunkEvents {
+    hipEvent_t h2d0 = nullptr, h2d1 = nullptr, c0 = nullptr, c1 = nullptr,
+               d2h0 = nullptr, d2h1 = nullptr;
+};
+
+struct Pipeline {
+    Plan *plan = nullptr;
+    uint64_t bytes = 0;
+    hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    void *dev[kDevSlots] = {nullptr, nullptr, nullptr};
+    std::vector<ChunkEvents> ev;  // one set per chunk in flight ring
+    int ring = 0;
+
+    int init(Plan *p, int ring_len)
+    {
+        plan = p;
+        ring = ring_len;
+        bytes = p->batch * p->n * sizeof(c32);
+        hipError_t e;
+        for (hipStream_t *s : {&s_in, &s_comp, &s_out})
+            if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess)
+                return hip_error(e, "hipStreamCreate");
+        for (int i = 0; i < kDevSlots; ++i)
+            if ((e = hipMalloc(&dev[i], bytes)) != hipSuccess) {
+                dev[i] = nullptr;
+                (void)hipGetLastError();
+                return set_error(FFT_ERR_OUT_OF_MEMORY, "device chunk buffer of %llu bytes",
+                                 (unsigned long long)bytes);
+            }
+        ev.resize(ring);
+        for (auto &c : ev)
+            for (hipEvent_t *q : {&c.h2d0, &c.h2d1, &c.c0, &c.c1, &c.d2h0, &c.d2h1})
+                if ((e = hipEventCreate(q)) != hipSuccess)
+                    return hip_error(e, "hipEventCreate");
+        return FFT_OK;
+    }
+
+    ~Pipeline()
+    {
+        for (hipStream_t s : {s_in, s_comp, s_out})
+            if (s)
+                (void)hipStreamSynchronize(s);
+        for (auto &c : ev)
+            for (hipEvent_t q : {c.h2d0, c.h2d1, c.c0, c.c1, c.d2h0, c.d2h1})
+                if (q)
+                    (void)hipEventDestroy(q);
+        for (void *d : dev)
+            if (d)
+                (void)hipFree(d);
+        for (hipStream_t s : {s_in, s_comp, s_out})
+            if (s)
+                (void)hipStreamDestroy(s);
+    }
+
+    // enqueue chunk c: host src -> device slot -> transform -> host dst
+    int issue(uint64_t c, const void *src, void *dst)
+    {
+        ChunkEvents &E = ev[c % ring];
+        void *d = dev[c % kDevSlots];
+        hipError_t e;
+        if (c >= (uint64_t)kDevSlots) {
+            // device slot free once the copy-out of chunk c - kDevSlots is done
+            ChunkEvents &P = ev[(c - kDevSlots) % ring];
+            if ((e = hipStreamWaitEvent(s_in, P.d2h1, 0)) != hipSuccess)
+                return hip_error(e, "hipStreamWaitEvent");
+        }
+        (void)hipEventRecord(E.h2d0, s_in);
+        if ((e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s_in)) != hipSuccess)
+            return hip_error(e, "host-to-device copy");
+        (void)hipEventRecord(E.h2d1, s_in);
+        (void)hipStreamWaitEvent(s_comp, E.h2d1, 0);
+        (void)hipEventRecord(E.c0, s_comp);
+        int st = plan_enqueue(plan, d, d, plan->batch, s_comp);
+        if (st != FFT_OK)
+            return st;
+        (void)hipEventRecord(E.c1, s_comp);
+        (void)hipStreamWaitEvent(s_out, E.c1, 0);
+        (void)hipEventRecord(E.d2h0, s_out);
+        if ((e = hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToHost, s_out)) != hipSuccess)
+            return hip_error(e, "device-to-host copy");
+        (void)hipEventRecord(E.d2h1, s_out);
+        return FFT_OK;
+    }
+
+    // block until chunk c is back on the host; add its GPU times to stats
+    int wait_chunk(uint64_t c, fft_stream_stats_t *st)
+    {
+        ChunkEvents &E = ev[c % ring];
+        hipError_t e = hipEventSynchronize(E.d2h1);
+        if (e != hipSuccess)
+            return hip_error(e, "hipEventSynchronize");
+        float a = 0, b = 0, d = 0;
+        (void)hipEventElapsedTime(&a, E.h2d0, E.h2d1);
+        (void)hipEventElapsedTime(&b, E.c0, E.c1);
+        (void)hipEventElapsedTime(&d, E.d2h0, E.d2h1);
+        if (st) {
+            st->h2d_s += a * 1e-3;
+            st->compute_s += b * 1e-3;
+            st->d2h_s += d * 1e-3;
+            st->bytes_h2d += bytes;
+            st->bytes_d2h += bytes;
+        }
+        return FFT_OK;
+    }
+
+    // block until chunk c's input has left host slot memory
+    int wait_input_consumed(uint64_t c)
+    {
+        hipError_t e = hipEventSynchronize(ev[c % ring].h2d1);
+        return e == hipSuccess ? FFT_OK : hip_error(e, "hipEventSynchronize");
+    }
+};
+
+struct PinnedRing {
+    std::vector<void *> in, out;
+    uint64_t bytes = 0;
+    ~PinnedRing() { release(); }
+    void release()
+    {
+        for (void *p : in)
+            if (p)
+                (void)hipHostFree(p);
+        for (void *p : out)
+            if (p)
+                (void)hipHostFree(p);
+        in.clear();
+        out.clear();
+    }
+    int reserve(int slots, uint64_t b)
+    {
+        if ((int)in.size() == slots && bytes == b)
+            return FFT_OK;
+        release();
+        bytes = b;
+        in.assign(slots, nullptr);
+        out.assign(slots, nullptr);
+        for (int i = 0; i < slots; ++i) {
+            if (hipHostMalloc(&in[i], b, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc(&out[i], b, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                release();
+                return set_error(FFT_ERR_OUT_OF_MEMORY, "pinned host slot of %llu bytes",
+                                 (unsigned long long)b);
+            }
+        }
+        return FFT_OK;
+    }
+};
+
+}  // namespace
+
+// pinned ring kept with the plan between calls (freed with the plan)
+struct StreamState {
+    PinnedRing ring;
+};
+
+void stream_state_free(Plan *p)
+{
+    delete static_cast<StreamState *>(p->stream_state);
+    p->stream_state = nullptr;
+}
+
+}  // namespace fftseg
+
+using namespace fftseg;
+
+extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn fill,
+                               fft_drain_fn drain, void *user, int n_slots,
+                               uint64_t *failed_chunk, fft_stream_stats_t *stats)
+{
+    try {
+        Plan *p = reinterpret_cast<Plan *>(plan);
+        if (!p)
+            return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+        if (!fill)
+            return set_error(FFT_ERR_INVALID_ARG, "fill callback is NULL");
+        if (n_slots < 2 || n_slots > 64)
+            return set_error(FFT_ERR_INVALID_ARG, "n_slots must be in [2, 64]");
+        if (failed_chunk)
+            *failed_chunk = UINT64_MAX;
+        if (stats)
+            std::memset(stats, 0, sizeof(*stats));
+        if (n_chunks == 0)
+            return set_ok();
+        const double t_start = now_s();
+        if (!p->stream_state)
+            p->stream_state = new StreamState();
+        StreamState *S = static_cast<StreamState *>(p->stream_state);
+        const uint64_t bytes = p->batch * p->n * sizeof(c32);
+        int st = S->ring.reserve(n_slots, bytes);
+        if (st != FFT_OK)
+            return st;
+        Pipeline pl;
+        if ((st = pl.init(p, std::max(n_slots, kDevSlots) + 1)) != FFT_OK)
+            return st;
+        const uint64_t lag = (uint64_t)n_slots - 1;  // chunks in flight before a drain
+        uint64_t drained = 0;
+        int fail = FFT_OK;
+        uint64_t fail_at = UINT64_MAX;
+        auto drain_one = [&](uint64_t c) -> int {
+            int s2 = pl.wait_chunk(c, stats);
+            if (s2 != FFT_OK)
+                return s2;
+            if (drain) {
+                const double t0 = now_s();
+                const int rc = drain(user, c, S->ring.out[c % n_slots], bytes);
+                if (stats)
+                    stats->drain_s += now_s() - t0;
+                if (rc != 0)
+                    return set_error(FFT_ERR_CALLBACK, "drain callback returned %d at chunk %llu",
+                                     rc, (unsigned long long)c);
+            }
+            if (stats)
+                stats->chunks_done = c + 1;
+            return FFT_OK;
+        };
+        for (uint64_t c = 0; c < n_chunks; ++c) {
+            if (c >= (uint64_t)n_slots && (st = pl.wait_input_consumed(c - n_slots)) != FFT_OK) {
+                fail = st;
+                fail_at = c;
+                break;
+            }
+            const double t0 = now_s();
+            const int rc = fill(user, c, S->ring.in[c % n_slots], bytes);
+            if (stats)
+                stats->fill_s += now_s() - t0;
+            if (rc != 0) {
+                fail = set_error(FFT_ERR_CALLBACK, "fill callback returned %d at chunk %llu", rc,
+                                 (unsigned long long)c);
+                fail_at = c;
+                break;
+            }
+            if ((st = pl.issue(c, S->ring.in[c % n_slots], S->ring.out[c % n_slots])) != FFT_OK) {
+                fail = st;
+                fail_at = c;
+                break;
+            }
+            if (c >= lag) {
+                if ((st = drain_one(drained)) != FFT_OK) {
+                    fail = st;
+                    fail_at = drained;
+                    break;
+                }
+                ++drained;
+            }
+        }
+        // finish what was issued before any failure
+        const uint64_t issued_end = fail == FFT_OK ? n_chunks : fail_at;
+        while (fail == FFT_OK && drained < issued_end) {
+            if ((st = drain_one(drained)) != FFT_OK) {
+                fail = st;
+                fail_at = drained;
+                break;
+            }
+            ++drained;
+        }
+        (void)hipStreamSynchronize(pl.s_in);
+        (void)hipStreamSynchronize(pl.s_comp);
+        (void)hipStreamSynchronize(pl.s_out);
+        if (fail != FFT_OK) {
+            // chunks below the failing one are handed out; a drain that
+            // fails on the way becomes the reported failure
+            while (drained < fail_at) {
+                if (drain_one(drained) != FFT_OK) {
+                    fail_at = drained;
+                    break;
+                }
+                ++drained;
+            }
+            if (failed_chunk)
+                *failed_chunk = fail_at;
+            if (stats)
+                stats->wall_s = now_s() - t_start;
+            return last_status();
+        }
+        if (stats)
+            stats->wall_s = now_s() - t_start;
+        return set_ok();
+    } catch (...) {
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+extern "C" int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
+                                      void *const *host_in, int n_in,
+                                      void *const *host_out, int n_out, int n_slots,
+                                      fft_stream_stats_t *stats)
+{
+    try {
+        Plan *p = reinterpret_cast<Plan *>(plan);
+        if (!p)
+            return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+        if (!host_in || !host_out || n_in < 1 || n_out < 1)
+            return set_error(FFT_ERR_INVALID_ARG, "host buffer lists are empty");
+        if (n_slots < 2 || n_slots > 64)
+            return set_error(FFT_ERR_INVALID_ARG, "n_slots must be in [2, 64]");
+        for (int i = 0; i < n_in; ++i)
+            if (!host_in[i])
+                return set_error(FFT_ERR_INVALID_ARG, "host_in[%d] is NULL", i);
+        for (int i = 0; i < n_out; ++i)
+            if (!host_out[i])
+                return set_error(FFT_ERR_INVALID_ARG, "host_out[%d] is NULL", i);
+        if (stats)
+            std::memset(stats, 0, sizeof(*stats));
+        if (n_chunks == 0)
+            return set_ok();
+        const double t_start = now_s();
+        Pipeline pl;
+        int st = pl.init(p, n_slots + kDevSlots);
+        if (st != FFT_OK)
+            return st;
+        const uint64_t lag = (uint64_t)n_slots - 1;
+        uint64_t waited = 0;
+        for (uint64_t c = 0; c < n_chunks; ++c) {
+            if ((st = pl.issue(c, host_in[c % n_in], host_out[c % n_out])) != FFT_OK)
+                return st;
+            if (c >= lag) {
+                if ((st = pl.wait_chunk(waited, stats)) != FFT_OK)
+                    return st;
+                ++waited;
+                if (stats)
+                    stats->chunks_done = waited;
+            }
+        }
+        while (waited < n_chunks) {
+            if ((st = pl.wait_chunk(waited, stats)) != FFT_OK)
+                return st;
+            ++waited;
+            if (stats)
+                stats->chunks_done = waited;
+        }
+        if (stats)
+            stats->wall_s = now_s() - t_start;
+        return set_ok();
+    } catch (...) {
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}

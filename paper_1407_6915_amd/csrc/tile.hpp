@@ -1,0 +1,413 @@
+// Stockham (self-sorting) Cooley-Tukey stages for a tile of G independent
+// transforms of length M held by one workgroup, T threads per transform.
+//
+// With radices R_0 .. R_{s-1} (product M) and L = R_0 * .. * R_{i-1}, stage i
+// does M/R_i butterflies; butterfly b reads
+//     a[b + r * M/R_i],  r = 0..R_i-1,
+// multiplies element r by W_{L R_i}^{r (b mod L)}, takes the R_i-point DFT
+// in registers and writes element r to
+//     a'[(b / L) * L R_i + (b mod L) + r * L].
+// After the last stage a holds the DFT in natural order: the digit-reversal
+// permutation of the textbook Cooley-Tukey form is folded into the write
+// index of every stage.  Stage 0 (L = 1, no twiddles) reads a[b + r M/R_0]
+// and the last stage (L R = M) writes a'[b + r M/R_last]: both are unit
+// stride across consecutive butterflies, so with consecutive lanes on
+// consecutive butterflies the global loads and stores coalesce.  The stages
+// in between exchange data through LDS.
+//
+// Twiddles W_{L R}^{m'} = W_M^{m' M/(L R)} come from a table of the forward
+// roots W_M^m = exp(-2 pi i m / M), m < M, evaluated in FP64 and rounded
+// once to float32 on the host; the inverse conjugates them.
+#pragma once
+
+#include "radix.hpp"
+
+namespace fftseg {
+
+template <int... Rs>
+struct Radices {
+    static constexpr int count = sizeof...(Rs);
+    static constexpr int at(int i)
+    {
+        constexpr int a[] = {Rs...};
+        return a[i];
+    }
+    static constexpr long long product() { return (1LL * ... * Rs); }
+    static constexpr int max_radix()
+    {
+        int m = 0;
+        for (int i = 0; i < count; ++i)
+            m = at(i) > m ? at(i) : m;
+        return m;
+    }
+};
+
+// Transform shape: length M, T threads per transform, radix list.
+template <int M_, int T_, class Rad_>
+struct Shape {
+    static constexpr int M = M_;
+    static constexpr int T = T_;
+    using Rad = Rad_;
+    static constexpr int NS = Rad::count;
+    static_assert(Rad::product() == M, "radices must multiply to M");
+    static constexpr int units(int r) { return (M / r + T - 1) / T; }
+    static constexpr int max_e()
+    {
+        int m = 1;
+        for (int i = 0; i < NS; ++i) {
+            int e = units(Rad::at(i)) * Rad::at(i);
+            m = e > m ? e : m;
+        }
+        return m;
+    }
+    static constexpr int kMaxE = max_e();  // complex values per thread
+};
+
+template <class Sh, int I, int L>
+struct Stage {
+    static constexpr int R = Sh::Rad::at(I);
+    static constexpr int NB = Sh::M / R;           // butterflies
+    static constexpr int U = (NB + Sh::T - 1) / Sh::T;  // per thread
+    static constexpr bool kFull = NB % Sh::T == 0;
+    static constexpr bool kLast = I + 1 == Sh::NS;
+    static constexpr int kTwStride = Sh::M / (L * R);
+};
+
+// v[u*R + r] <- get(b + r*NB) for this thread's butterflies b = t + u*T
+template <class St, class Sh, class Get>
+__device__ __forceinline__ void st_gather(c32 *v, int t, Get &&get)
+{
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+#pragma unroll
+            for (int r = 0; r < St::R; ++r)
+                v[u * St::R + r] = get(b + r * St::NB);
+        }
+    }
+}
+
+// twiddle + R-point DFT of this thread's butterflies
+template <class St, class Sh, int L, int D>
+__device__ __forceinline__ void st_compute(c32 *v, int t,
+                                           const c32 *__restrict__ tw)
+{
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            if constexpr (L > 1) {
+                const int k = b % L;
+#pragma unroll
+                for (int r = 1; r < St::R; ++r)
+                    v[u * St::R + r] = twiddle<D>(
+                        v[u * St::R + r], tw[r * k * St::kTwStride]);
+            }
+            dft<St::R, D>(v + u * St::R);
+        }
+    }
+}
+
+// put(index, value) for the stage outputs a'[(b/L) L R + b%L + r L]
+template <class St, class Sh, int L, class Put>
+__device__ __forceinline__ void st_scatter(const c32 *v, int t, Put &&put)
+{
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            const int base = (b / L) * (L * St::R) + (b % L);
+#pragma unroll
+            for (int r = 0; r < St::R; ++r)
+                put(base + r * L, v[u * St::R + r]);
+        }
+    }
+}
+
+// Run stages I.. of a tile.  Pol supplies the lane mapping per stage
+// (col<I>, thr<I>), the LDS address of element i of tile column c, and the
+// final store (which sees the last stage's outputs at b + r*NB).
+template <class Sh, class Pol, int D, int I, int L>
+__device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
+                                         const c32 *__restrict__ tw, int tid,
+                                         const typename Pol::Ctx &ctx)
+{
+    using St = Stage<Sh, I, L>;
+    const int c = Pol::template col<I>(tid);
+    const int t = Pol::template thr<I>(tid);
+    st_compute<St, Sh, L, D>(v, t, tw);
+    if constexpr (St::kLast) {
+        Pol::template store<St, D>(v, t, c, ctx);
+    } else {
+        st_scatter<St, Sh, L>(v, t, [&](int i, c32 a) { lds[Pol::lds(c, i)] = a; });
+        __syncthreads();
+        using Nx = Stage<Sh, I + 1, L * St::R>;
+        const int c2 = Pol::template col<I + 1>(tid);
+        const int t2 = Pol::template thr<I + 1>(tid);
+        st_gather<Nx, Sh>(v, t2, [&](int i) { return lds[Pol::lds(c2, i)]; });
+        __syncthreads();
+        tile_run<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, ctx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single pass: S whole segments per workgroup, each owned by T threads.
+//   lane mapping: segment slot = tid / T, thread t = tid % T (all stages);
+//   LDS: slot * SegStride + i + (i >> PS) (one pad element every 2^PS).
+template <class Sh, int S_, int PS_>
+struct SinglePassPolicy {
+    static constexpr int S = S_;
+    static constexpr int PS = PS_;
+    static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
+    static constexpr int kSegStride = pad(Sh::M - 1) + 1;
+    static constexpr int kLdsElems = Sh::NS > 1 ? S * kSegStride : 1;
+    static constexpr int kThreads = Sh::T * S;
+
+    struct Ctx {
+        c32 *y;       // output segment base of this thread's slot
+        bool valid;   // the slot holds a real segment
+    };
+    template <int I>
+    static __device__ __forceinline__ int col(int tid) { return S == 1 ? 0 : tid / Sh::T; }
+    template <int I>
+    static __device__ __forceinline__ int thr(int tid) { return S == 1 ? tid : tid % Sh::T; }
+    static __device__ __forceinline__ int lds(int c, int i) { return c * kSegStride + pad(i); }
+
+    template <class St, int D>
+    static __device__ __forceinline__ void store(const c32 *v, int t, int, const Ctx &ctx)
+    {
+        if (!ctx.valid)
+            return;
+#pragma unroll
+        for (int u = 0; u < St::U; ++u) {
+            const int b = t + u * Sh::T;
+            if (St::kFull || b < St::NB) {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    ctx.y[b + r * St::NB] = v[u * St::R + r];
+            }
+        }
+    }
+};
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads)
+    single_pass_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                       uint64_t batch)
+{
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int tid = threadIdx.x;
+    const int slot = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const uint64_t seg = g * Pol::S + slot;
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch};
+        const c32 *x = in + seg * Sh::M;
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        if (ctx.valid)
+            st_gather<S0, Sh>(v, t, [&](int i) { return x[i]; });
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Four-step split N = N1 * N2 for segments longer than one LDS tile.
+// With n = n1*N2 + n2 and k = k1 + N1*k2:
+//   X[k1 + N1 k2] = sum_{n2} W_{N2}^{n2 k2} [ W_N^{n2 k1} sum_{n1} x[n1 N2 + n2] W_{N1}^{n1 k1} ]
+// Pass A: for every column n2, the N1-point DFT over n1 (stride N2), times
+//         W_N^{n2 k1}, stored as Y[k1 N2 + n2] (same layout as the input).
+// Pass B: for every row k1 of Y, the N2-point DFT over n2 (contiguous),
+//         stored transposed as X[k1 + N1 k2].
+// A workgroup owns C adjacent columns (pass A) or C adjacent rows (pass B)
+// of one segment, so every global access moves runs of C*8 contiguous bytes.
+// W_N^m (m = n2*k1 < N) is the product of two table entries
+// th[m >> sh] * tl[m & (2^sh - 1)], each evaluated in FP64 and rounded once.
+
+struct FourStepCtx {
+    const c32 *x;   // pass A: segment input;     pass B: segment of Y
+    c32 *y;         // pass A: segment of Y;      pass B: segment output
+    int first;      // first column (A) / row (B) of the tile
+    int n1, n2;
+    const c32 *__restrict__ tl;
+    const c32 *__restrict__ th;
+    int sh;
+    bool valid;
+};
+
+// Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
+template <class Sh, int C_, int PS_>
+struct ColumnPolicy {
+    static constexpr int C = C_;
+    static constexpr int PS = PS_;
+    static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
+    static constexpr int kLdsElems = (pad(Sh::M - 1) + 1) * C;
+    static constexpr int kThreads = Sh::T * C;
+    using Ctx = FourStepCtx;
+    template <int I>
+    static __device__ __forceinline__ int col(int tid) { return tid % C; }
+    template <int I>
+    static __device__ __forceinline__ int thr(int tid) { return tid / C; }
+    static __device__ __forceinline__ int lds(int c, int i) { return pad(i) * C + c; }
+
+    template <class St, int D>
+    static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
+    {
+        if (!ctx.valid)
+            return;
+        const unsigned n2 = (unsigned)(ctx.first + c);
+        const unsigned mask = (1u << ctx.sh) - 1u;
+#pragma unroll
+        for (int u = 0; u < St::U; ++u) {
+            const int b = t + u * Sh::T;
+            if (St::kFull || b < St::NB) {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r) {
+                    const unsigned k1 = (unsigned)(b + r * St::NB);
+                    const unsigned m = n2 * k1;
+                    const c32 w = cmul(ctx.th[m >> ctx.sh], ctx.tl[m & mask]);
+                    ctx.y[(size_t)k1 * ctx.n2 + n2] = twiddle<D>(v[u * St::R + r], w);
+                }
+            }
+        }
+    }
+};
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads)
+    four_step_columns_kernel(const c32 *in, c32 *ybuf, const c32 *__restrict__ tw,
+                             const c32 *__restrict__ tl, const c32 *__restrict__ th,
+                             int sh, int n2, uint64_t batch)
+{
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int tid = threadIdx.x;
+    const int c = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
+    const uint64_t blocks = (uint64_t)(n2 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+        const uint64_t seg = g / blocks;
+        const int first = (int)(g - seg * blocks) * Pol::C;
+        FourStepCtx ctx{in + seg * nseg, ybuf + seg * nseg, first, Sh::M, n2,
+                        tl, th, sh, true};
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        const c32 *x = ctx.x + first + c;
+        st_gather<S0, Sh>(v, t, [&](int i) { return x[(size_t)i * n2]; });
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
+// Pass B: lanes row-major (c = tid / T, t = tid % T) up to the last stage,
+// row-fastest (c = tid % C, t = tid / C) in the last stage so the
+// transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
+template <class Sh, int C_, int PS_>
+struct RowPolicy {
+    static constexpr int C = C_;
+    static constexpr int PS = PS_;
+    static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
+    static constexpr int kRow = (pad(Sh::M - 1) + 1) | 1;  // odd row stride
+    static constexpr int kLdsElems = kRow * C;
+    static constexpr int kThreads = Sh::T * C;
+    using Ctx = FourStepCtx;
+    template <int I>
+    static __device__ __forceinline__ int col(int tid)
+    {
+        return (I + 1 == Sh::NS) ? tid % C : tid / Sh::T;
+    }
+    template <int I>
+    static __device__ __forceinline__ int thr(int tid)
+    {
+        return (I + 1 == Sh::NS) ? tid / C : tid % Sh::T;
+    }
+    static __device__ __forceinline__ int lds(int c, int i) { return c * kRow + pad(i); }
+
+    template <class St, int D>
+    static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
+    {
+        if (!ctx.valid)
+            return;
+        c32 *y = ctx.y + ctx.first + c;
+#pragma unroll
+        for (int u = 0; u < St::U; ++u) {
+            const int b = t + u * Sh::T;
+            if (St::kFull || b < St::NB) {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    y[(size_t)(b + r * St::NB) * ctx.n1] = v[u * St::R + r];
+            }
+        }
+    }
+};
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads)
+    four_step_rows_kernel(const c32 *ybuf, c32 *out, const c32 *__restrict__ tw,
+                          int n1, uint64_t batch)
+{
+    static_assert(Sh::NS > 1, "the row pass changes lane mapping through LDS");
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int tid = threadIdx.x;
+    const int c = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n1;
+    const uint64_t blocks = (uint64_t)(n1 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+        const uint64_t seg = g / blocks;
+        const int first = (int)(g - seg * blocks) * Pol::C;
+        FourStepCtx ctx{ybuf + seg * nseg, out + seg * nseg, first, n1, Sh::M,
+                        nullptr, nullptr, 0, true};
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        const c32 *x = ctx.x + (size_t)(first + c) * Sh::M;
+        st_gather<S0, Sh>(v, t, [&](int i) { return x[i]; });
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fallback for lengths without a compiled tile: one launch per Stockham
+// stage over global memory, one thread per butterfly, radix R at run-time
+// stride L.  Twiddle W_N^m = th[m >> sh] * tl[m & mask] as in pass A.
+template <int R, int D>
+__global__ void __launch_bounds__(256)
+    stockham_global_stage_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tl,
+                                 const c32 *__restrict__ th, int sh,
+                                 uint64_t n, uint64_t l, uint64_t batch)
+{
+    const uint64_t nb = n / R;
+    const uint64_t total = nb * batch;
+    const uint64_t tw_stride = n / (l * R);
+    const unsigned mask = (1u << sh) - 1u;
+    for (uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t seg = gid / nb;
+        const uint64_t b = gid - seg * nb;
+        const c32 *x = in + seg * n;
+        c32 *y = out + seg * n;
+        c32 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = x[b + r * nb];
+        const uint64_t k = b % l;
+        if (l > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const unsigned m = (unsigned)(r * k * tw_stride);
+                v[r] = twiddle<D>(v[r], cmul(th[m >> sh], tl[m & mask]));
+            }
+        }
+        dft<R, D>(v);
+        const uint64_t base = (b / l) * (l * R) + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            y[base + r * l] = v[r];
+    }
+}
+
+}  // namespace fftseg

@@ -1,0 +1,76 @@
+"""The C-ABI library on a host without a GPU: it loads, exports every
+function include/*.h declares, and rejects bad arguments before touching
+the device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1407_6915_amd as fs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w \*]*?\b(fft_\w+)\s*\(", src, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "fft_plan_create" in names and "fft_exec_segments" in names
+    lib = ctypes.CDLL(fs.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 1, -1), "FFT_ERR_INVALID_ARG"),
+    ((1024, 0, -1), "FFT_ERR_INVALID_ARG"),
+    ((1024, 1, 0), "FFT_ERR_INVALID_ARG"),
+    ((1024, 1, 2), "FFT_ERR_INVALID_ARG"),
+    ((7, 1, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),
+    ((1024 * 7, 1, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),
+    ((1 << 25, 1, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),
+    ((1024, 1 << 62, -1), "FFT_ERR_INVALID_ARG"),
+])
+def test_create_rejects_bad_arguments(args, status):
+    with pytest.raises(fs.FFTError) as ei:
+        fs.Plan(*args)
+    assert ei.value.name == status
+    assert fs.lib().fft_last_status() == ei.value.status
+    assert fs.last_error()
+
+
+def test_null_plan_calls():
+    L = fs.lib()
+    assert L.fft_plan_destroy(None) == 0
+    assert L.fft_exec_segments(None, None, None, None) == -1
+    assert L.fft_plan_describe(None, None, 0) == -1
+    assert L.fft_plan_scratch_bytes(None) == 0
+
+
+def test_factorize_matches_lengths():
+    for n in (2, 16, 256, 1000, 1024, 1536, 4096, 6000, 16384, 65536, 3 ** 9,
+              2 * 3 * 5 * 7 * 0 + 30, 1 << 20):
+        r = fs.factorize(n)
+        p = 1
+        for v in r:
+            assert v in (2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 25, 32)
+            p *= v
+        assert p == n, (n, r)
+    assert fs.factorize(4096) == [16, 16, 16]
+    with pytest.raises(fs.FFTError):
+        fs.factorize(14)
+
+
+def test_variants_compiled_for_workload_lengths():
+    for n in (256, 1000, 1024, 1536, 4096, 6000, 16384):
+        assert fs.variant_count(n) >= 2, n

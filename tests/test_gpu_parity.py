@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element,
+per-segment relative L2 error <= 5e-7 * log2(N)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1407_6915_amd as fs
+from siggen import workloads
+
+from gpu_helpers import announce, check, noise, run
+
+pytestmark = pytest.mark.gpu
+
+SINGLE = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1000, 1024, 1536, 2048, 4096,
+          6000, 8192, 16384]
+FOUR_STEP = [1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 20]
+FALLBACK = [3, 5, 6, 9, 12, 15, 25, 27, 30, 45, 81, 100, 125, 243, 360,
+            3 ** 9, 5 ** 6, 2 * 3 ** 9]
+
+
+def ragged_batch(n):
+    """A batch spanning several workgroups with a ragged tail."""
+    if n <= 64:
+        return 200 + 7
+    if n <= 4096:
+        return max(3, (1 << 18) // n) + 3
+    return 3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fs.lib()
+    yield
+
+
+def test_small_workload_all_segments():
+    n, b = 1024, 1024
+    announce("1024-point x 1024 segments, all vs recursive oracle, 64 vs direct")
+    x = workloads.small_signal().segments(0, b)
+    y = run(n, x)
+    check(n, y, x, what="all segments")
+    idx = np.random.default_rng(0).choice(b, 64, replace=False)
+    ref = oracle.dft_direct(x[idx], n)
+    assert np.all(oracle.rel_l2(y[idx], ref) <= oracle.tolerance(n))
+    # the three unit tones stand out as spikes of height ~N in every segment
+    for b0, _, _ in workloads.small_signal().tones:
+        assert np.all(np.abs(y[:, b0]) > 0.9 * n)
+
+
+@pytest.mark.parametrize("n", SINGLE + FOUR_STEP + FALLBACK)
+@pytest.mark.parametrize("direction", [fs.FORWARD, fs.INVERSE])
+def test_lengths(n, direction):
+    b = ragged_batch(n)
+    announce("n=%d batch=%d dir=%d" % (n, b, direction))
+    x = noise(n, b, seed=n)
+    check(n, run(n, x, direction), x, direction)
+
+
+@pytest.mark.parametrize("n", [256, 512, 1000, 1024, 1536, 2048, 4096, 6000, 8192, 16384])
+def test_every_variant(n):
+    for v in range(fs.variant_count(n)):
+        b = ragged_batch(n)
+        announce("n=%d variant=%d batch=%d" % (n, v, b))
+        x = noise(n, b, seed=10 * n + v)
+        for d in (fs.FORWARD, fs.INVERSE):
+            check(n, run(n, x, d, variant=v), x, d, what="variant %d dir %d" % (v, d))
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 6000, 1 << 16, 3 ** 9, 5])
+def test_in_place_equals_out_of_place_and_deterministic(n):
+    b = ragged_batch(n)
+    announce("in place n=%d" % n)
+    x = noise(n, b, seed=7)
+    a = run(n, x)
+    assert np.array_equal(a, run(n, x, inplace=True))
+    assert np.array_equal(a, run(n, x))
+
+
+@pytest.mark.parametrize("n", [1024, 1536, 1 << 16])
+def test_segment_locality_and_order(n):
+    b = 9
+    announce("locality n=%d" % n)
+    x = noise(n, b, seed=3)
+    y = run(n, x)
+    x2 = x.copy()
+    x2[4] += noise(n, 1, seed=4)[0]
+    y2 = run(n, x2)
+    assert np.array_equal(np.delete(y, 4, 0), np.delete(y2, 4, 0))
+    assert not np.array_equal(y[4], y2[4])
+    perm = np.random.default_rng(1).permutation(b)
+    assert np.array_equal(run(n, x[perm]), y[perm])
+
+
+@pytest.mark.parametrize("n", [1000, 4096, 1 << 20])
+def test_round_trip(n):
+    b = 2 if n > 4096 else 33
+    announce("round trip n=%d" % n)
+    x = noise(n, b, seed=11)
+    z = run(n, run(n, x), fs.INVERSE) / n
+    err = oracle.rel_l2(z, x.astype(np.complex128))
+    assert np.all(err <= 2 * oracle.tolerance(n)), err.max()
+
+
+def test_closed_forms():
+    announce("closed forms")
+    n = 4096
+    x = np.zeros((3, n), np.complex64)
+    x[0, 0] = 1                     # impulse: flat spectrum
+    x[1, 5] = 1                     # shifted impulse: phase ramp
+    k0 = 1234
+    t = np.arange(n)
+    x[2] = np.exp(2j * np.pi * ((k0 * t) % n) / n)   # bin tone: one spike
+    y = run(n, x).astype(np.complex128)
+    assert np.allclose(y[0], 1, atol=1e-6)
+    k = np.arange(n)
+    assert np.allclose(y[1], np.exp(-2j * np.pi * ((5 * k) % n) / n), atol=1e-6)
+    spike = np.zeros(n)
+    spike[k0] = n
+    assert np.abs(y[2] - spike).max() < 1e-6 * n
+    # unit chirp exp(i pi t^2/N): X[k] = sqrt(N) e^{i pi/4} e^{-i pi k^2/N}
+    n = 1 << 20
+    t = np.arange(n, dtype=np.int64)
+    c = np.exp(1j * np.pi * ((t * t) % (2 * n)) / n).astype(np.complex64)
+    want = np.sqrt(n) * np.exp(1j * np.pi / 4) * np.exp(-1j * np.pi * ((t * t) % (2 * n)) / n)
+    yc = run(n, c[None, :])[0]
+    assert oracle.rel_l2(yc[None], want[None])[0] <= oracle.tolerance(n)
+
+
+def test_length_one_is_identity():
+    announce("n=1")
+    x = noise(1, 10, seed=5)
+    assert np.array_equal(run(1, x), x)
+    assert np.array_equal(run(1, x, fs.INVERSE), x)
+
+
+def test_zero_input_gives_exact_zero():
+    announce("zeros")
+    for n in (4096, 1 << 16, 3 ** 9):
+        x = np.zeros((2, n), np.complex64)
+        assert not np.any(run(n, x))
+
+
+# ----- argument checks with a live device ---------------------------------
+
+def _hip():
+    return ctypes.CDLL("libamdhip64.so")
+
+
+def test_exec_argument_errors():
+    import torch
+    announce("exec argument errors")
+    n, b = 1024, 4
+    x = torch.zeros(n * b + 8, dtype=torch.complex64, device="cuda")
+    p = fs.Plan(n, b)
+    base = x.data_ptr()
+    with pytest.raises(fs.FFTError) as e:
+        p.exec_ptr(base, base + 8 * 8)              # partial overlap
+    assert e.value.name == "FFT_ERR_OVERLAP"
+    with pytest.raises(fs.FFTError) as e:
+        p.exec_ptr(base + 4, base + 4)              # misaligned
+    assert e.value.name == "FFT_ERR_ALIGNMENT"
+    with pytest.raises(fs.FFTError) as e:
+        p.exec_ptr(base, 0)
+    assert e.value.name == "FFT_ERR_INVALID_ARG"
+    with pytest.raises(fs.FFTError) as e:
+        p.exec_ptr(base, base, batch=b + 1)
+    assert e.value.name == "FFT_ERR_INVALID_ARG"
+    p.exec_ptr(base, base, batch=b - 1)             # a prefix is fine
+    torch.cuda.synchronize()
+    p.close()
+
+
+def test_exec_rejects_memory_it_cannot_use():
+    """Buffers the library must refuse: too short for the batch, or
+    ordinary host memory.  Each case runs only after checking, with the HIP
+    runtime directly, that the runtime reports the buffer the way the
+    library's check relies on, so no kernel can run on a bad pointer."""
+    import torch
+    announce("exec bounds / host pointer")
+    hip = _hip()
+    torch.cuda.synchronize()
+    p = ctypes.c_void_p()
+    nbytes = 1 << 20
+    assert hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(nbytes)) == 0
+    try:
+        base, size = ctypes.c_void_p(), ctypes.c_size_t()
+        rc = hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), p)
+        if rc == 0 and base.value == p.value and size.value == nbytes:
+            plan = fs.Plan(1024, 2 * nbytes // 8 // 1024)   # needs 2 MiB
+            with pytest.raises(fs.FFTError) as e:
+                plan.exec_ptr(p.value, p.value)
+            assert e.value.name == "FFT_ERR_BOUNDS"
+            plan.close()
+    finally:
+        hip.hipFree(p)
+    host = np.zeros(1024 * 2, np.complex64)
+    hp = ctypes.c_void_p(host.ctypes.data)
+    base, size = ctypes.c_void_p(), ctypes.c_size_t()
+    attr = (ctypes.c_int * 32)()
+    range_rc = hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), hp)
+    attr_rc = hip.hipPointerGetAttributes(attr, hp)
+    hip.hipGetLastError()
+    # hipMemoryTypeDevice = 2, hipMemoryTypeManaged = 3
+    if range_rc != 0 and (attr_rc != 0 or attr[0] not in (2, 3)):
+        plan = fs.Plan(1024, 2)
+        with pytest.raises(fs.FFTError) as e:
+            plan.exec_ptr(host.ctypes.data, host.ctypes.data)
+        assert e.value.name == "FFT_ERR_INVALID_ARG"
+        plan.close()
+
+
+def test_plan_describe():
+    announce("describe")
+    d = fs.Plan(4096, 8).describe()
+    assert d["kind"] == "single_pass" and d["radices"] == [16, 16, 16]
+    d = fs.Plan(1 << 20, 2).describe()
+    assert d["kind"] == "four_step" and d["n1"] * d["n2"] == 1 << 20
+    d = fs.Plan(3 ** 9, 2).describe()
+    assert d["kind"] == "radix_stages"
