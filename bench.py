@@ -71,21 +71,7 @@ def cpu_baseline(x_host, n: int, budget_s: float):
                       "radix-2/3/5 DFT)" % (m, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=262144)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this path shards by contiguous segment "
-              "ranges with no communication, and no multi-GPU run is part of it "
-              "(got --gpus %d)" % args.gpus, file=sys.stderr)
-        return 2
-
+def bench_large(args):
     import torch
     import paper_1407_6915_amd as fs
     from siggen import workloads
@@ -145,7 +131,8 @@ def main():
         "config": {"workload": workloads.LARGE["name"], "segment_len": n, "batch": b,
                    "direction": "forward", "samples": samples,
                    "bytes_per_buffer": samples * 8, "kernel": desc.get("kind"),
-                   "radices": desc.get("radices"), "parallelism": "single GPU"},
+                   "radices": desc.get("radices"), "variant": desc.get("variant"),
+                   "grid_mult": desc.get("grid_mult"), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -153,6 +140,20 @@ def main():
                      "kernel_avg_us": round(avg_kernel_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if args.copy_reference:
+        # a plain copy of the same size, as the practical bandwidth reference
+        # (and the known-size kernel that scales the hardware byte counters)
+        for _ in range(2):
+            yd.copy_(xd)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(args.steps):
+            yd.copy_(xd)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        out["copy_reference_GBps"] = round(alg_bytes / (c0.elapsed_time(c1) / args.steps / 1e3)
+                                           / 1e9, 1)
     plan.close()
     del xd, yd
     torch.cuda.synchronize()
@@ -160,6 +161,36 @@ def main():
         out["cpu_baseline"] = cpu_baseline(x_host, n, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=262144)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also time a plain device copy of the same size")
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "small", "uneven", "streamed", "serving"],
+                    help="large = the 4096-point x 262144 batch (the reported metric); "
+                         "the others print their own JSON line")
+    ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")
+    ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per rate")
+    ap.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.0,1.2",
+                    help="serving: arrival rates as fractions of the plain path's saturation")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this path shards by contiguous segment "
+              "ranges with no communication, and no multi-GPU run is part of it "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        return 2
+    if args.workload == "large":
+        return bench_large(args)
+    import bench_workloads
+    return bench_workloads.run(args)
 
 
 if __name__ == "__main__":

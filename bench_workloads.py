@@ -1,0 +1,251 @@
+"""The other workloads of bench.py (``--workload small|uneven|streamed|
+serving``).  Each prints one JSON line.  All inputs are seeded synthetic
+signals (siggen); device buffers come from torch; every transform runs in
+libfftseg's kernels."""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import time
+
+import numpy as np
+
+FLOP = lambda n: 5.0 * n * math.log2(n) if n > 1 else 0.0  # noqa: E731
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(torch, fn, reps, warmup=2):
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def small(args):
+    import torch
+    import paper_1407_6915_amd as fs
+    from siggen import workloads
+    n, b = workloads.SMALL["seg_len"], workloads.SMALL["batch"]
+    x = workloads.small_signal().segments(0, b)
+    xd = torch.from_numpy(x.reshape(-1)).cuda()
+    yd = torch.empty_like(xd)
+    sh = torch.cuda.current_stream().cuda_stream
+    with fs.Plan(n, b) as p:
+        t = _time(torch, lambda: p.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
+        tg = _time(torch, lambda: p.exec_graph_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
+    print(json.dumps({"workload": workloads.SMALL["name"], "segment_len": n, "batch": b,
+                      "us_per_exec": round(t * 1e6, 2), "us_per_graph_exec": round(tg * 1e6, 2),
+                      "GFLOP/s": round(FLOP(n) * b / t / 1e9, 1),
+                      "GB/s": round(16 * n * b / t / 1e9, 1)}), flush=True)
+    return 0
+
+
+def uneven(args):
+    import torch
+    import paper_1407_6915_amd as fs
+    from siggen import workloads
+    lengths = workloads.uneven_lengths()
+    in_off = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+    total = int(lengths.sum())
+    sig = workloads.uneven_signal()
+    xd = torch.empty(total, dtype=torch.complex64, device="cuda")
+    chunk = 1 << 27
+    for a in range(0, total, chunk):
+        m = min(chunk, total - a)
+        xd[a:a + m].copy_(torch.from_numpy(sig.samples(a, m)))
+    yd = torch.empty_like(xd)
+    ent = np.zeros(len(lengths), dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                                        ("segment_len", "<u4"), ("job", "<u4")])
+    ent["in_off"] = ent["out_off"] = in_off
+    ent["segment_len"] = lengths
+    sh = torch.cuda.current_stream().cuda_stream
+    t_build = time.perf_counter()
+    wl = fs.WorkList(ent)
+    t_build = time.perf_counter() - t_build
+    t_wl = _time(torch, lambda: wl.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
+    t_graph = _time(torch, lambda: wl.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh, graph=True),
+                    args.steps)
+    wl.status()
+    desc = wl.describe()
+    wl.close()
+    # reference: one plain batched launch per length over length-sorted data
+    per_len = {}
+    bufs = {}
+    for n in workloads.UNEVEN_LENGTHS:
+        c = int((lengths == n).sum())
+        xs = torch.randn(c * n, dtype=torch.complex64, device="cuda")
+        bufs[n] = (xs, torch.empty_like(xs), fs.Plan(n, c))
+    del xd, yd
+
+    def all_lengths():
+        for n, (xs, ys, p) in bufs.items():
+            p.exec_ptr(xs.data_ptr(), ys.data_ptr(), sh)
+    t_plain = _time(torch, all_lengths, args.steps)
+    for n, (xs, ys, p) in bufs.items():
+        per_len[str(n)] = round(_time(torch, lambda: p.exec_ptr(xs.data_ptr(), ys.data_ptr(), sh),
+                                      max(3, args.steps // 4)) * 1e3, 3)
+        p.close()
+    flops = float(sum(FLOP(int(n)) for n in lengths))
+    comp = 16.0 * total
+    plan_bytes = float(sum(16 * n * (2 if n in (16384, 65536) else 1) for n in lengths))
+    out = {"workload": workloads.UNEVEN["name"], "segments": len(lengths), "samples": total,
+           "worklist": desc, "build_s": round(t_build, 3),
+           "persistent_ms": round(t_wl * 1e3, 3), "persistent_graph_ms": round(t_graph * 1e3, 3),
+           "per_length_plain_ms": round(t_plain * 1e3, 3), "per_length_ms": per_len,
+           "GFLOP/s": {"persistent": round(flops / t_wl / 1e9, 1),
+                       "persistent_graph": round(flops / t_graph / 1e9, 1),
+                       "per_length_plain": round(flops / t_plain / 1e9, 1)},
+           "compulsory_GB/s": {"persistent": round(comp / t_wl / 1e9, 1),
+                               "per_length_plain": round(comp / t_plain / 1e9, 1)},
+           "plan_GB/s_persistent": round(plan_bytes / t_wl / 1e9, 1),
+           "roofline_frac_compulsory": round(comp / t_wl / 1e9 / 8000.0, 4)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def streamed(args):
+    import torch
+    import oracle
+    import paper_1407_6915_amd as fs
+    from siggen import workloads
+    n, seg = workloads.LONG["seg_len"], workloads.LONG["chunk_segments"]
+    chunk_samples = n * seg
+    nbytes = chunk_samples * 8
+    sig = workloads.long_signal()
+    plan = fs.Plan(n, seg)
+    # host-link reference: plain pinned copies of one chunk each way
+    hb = torch.empty(chunk_samples, dtype=torch.complex64).pin_memory()
+    db = torch.empty(chunk_samples, dtype=torch.complex64, device="cuda")
+    t_h2d = _time(torch, lambda: db.copy_(hb, non_blocking=True), 3, 1)
+    t_d2h = _time(torch, lambda: hb.copy_(db, non_blocking=True), 3, 1)
+    del db
+    # (1) pre-generated pinned pool, cycled: the host link and the pipeline
+    pool = 4
+    t0 = time.perf_counter()
+    ins = [torch.empty(chunk_samples, dtype=torch.complex64).pin_memory() for _ in range(pool)]
+    outs = [torch.empty(chunk_samples, dtype=torch.complex64).pin_memory() for _ in range(pool)]
+    for c in range(pool):
+        sig.fill_ptr(c * chunk_samples, chunk_samples, ins[c].data_ptr())
+    t_pool = time.perf_counter() - t0
+    st = plan.exec_stream_pinned(args.chunks, [t.data_ptr() for t in ins],
+                                 [t.data_ptr() for t in outs], 3)
+    # spot checks: first and last segment of the last chunks written
+    errs = []
+    for c in range(max(0, args.chunks - pool), args.chunks):
+        slot = c % pool
+        for s in (0, seg - 1):
+            x = ins[slot][s * n:(s + 1) * n].numpy()
+            y = outs[slot][s * n:(s + 1) * n].numpy()
+            errs.append(float(oracle.rel_l2(y[None], oracle.fft_recursive(x, n))[0]))
+    gen_chunks = min(args.chunks, 8)
+    addr, src = sig.chunk_source(0, chunk_samples)
+    rc, failed, st_gen = plan.exec_stream(gen_chunks, (addr, src), None, 3)
+    plan.close()
+    moved = 2.0 * st["bytes_h2d"]
+    out = {"workload": workloads.LONG["name"], "segment_len": n, "segments_per_chunk": seg,
+           "chunk_bytes": nbytes, "chunks": args.chunks,
+           "signal_bytes": args.chunks * nbytes,
+           "pinned_copy_GBps": {"h2d": round(nbytes / t_h2d / 1e9, 2),
+                                "d2h": round(nbytes / t_d2h / 1e9, 2)},
+           "pipeline_pinned_pool": {
+               "wall_s": round(st["wall_s"], 3),
+               "host_link_GBps_each_way": round(st["bytes_h2d"] / st["wall_s"] / 1e9, 2),
+               "host_link_GBps_total": round(moved / st["wall_s"] / 1e9, 2),
+               "h2d_s": round(st["h2d_s"], 3), "d2h_s": round(st["d2h_s"], 3),
+               "transform_s": round(st["compute_s"], 3),
+               "transform_HBM_GBps": round(32.0 * chunk_samples * args.chunks /
+                                           max(st["compute_s"], 1e-9) / 1e9, 1),
+               "GFLOP/s": round(FLOP(n) * seg * args.chunks / st["wall_s"] / 1e9, 1),
+               "amdahl_parallel_fraction": round(st["compute_s"] /
+                                                 (st["compute_s"] + st["h2d_s"]), 4),
+               "pool_chunks": pool, "pool_fill_s": round(t_pool, 2),
+               "spot_check_max_rel_l2": max(errs), "bound": oracle.tolerance(n)},
+           "pipeline_generated": {
+               "status": rc, "chunks": gen_chunks, "wall_s": round(st_gen["wall_s"], 3),
+               "fill_s": round(st_gen["fill_s"], 3),
+               "host_link_GBps_each_way": round(st_gen["bytes_h2d"] /
+                                                max(st_gen["wall_s"], 1e-9) / 1e9, 2),
+               "generation_GBps": round(st_gen["bytes_h2d"] / max(st_gen["fill_s"], 1e-9)
+                                        / 1e9, 2)}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def serving(args):
+    import torch
+    import paper_1407_6915_amd as fs
+    from paper_1407_6915_amd.serve import GpuExecutor, JobState, serve, serve_fifo
+    from siggen import workloads
+    rng = np.random.default_rng(5)
+    pool_samples = 1 << 32                                 # 32 GiB pinned payload pool
+    t0 = time.perf_counter()
+    pool = torch.empty(pool_samples, dtype=torch.complex64).pin_memory()
+    outp = torch.empty(pool_samples, dtype=torch.complex64).pin_memory()
+    gen = workloads.job_signal(workloads.Job(0, 0.0, 4096, 1))
+    chunk = 1 << 28
+    for a in range(0, pool_samples, chunk):
+        gen.fill_ptr(a, chunk, pool.data_ptr() + a * 8)
+    t_pool = time.perf_counter() - t0
+    base_in, base_out = pool.data_ptr(), outp.data_ptr()
+
+    def job_states(rate, n_jobs, off):
+        js = []
+        for j in workloads.serving_jobs(rate, n_jobs, seed_offset=off):
+            start = int(rng.integers(0, pool_samples - j.samples)) & ~63
+            js.append(JobState(j.index, j.arrival_s, j.seg_len, j.n_seg,
+                               base_in + start * 8, base_out + start * 8))
+        return js
+
+    lengths = workloads.SERVING_LENGTHS
+    cap = 1 << 30
+    plans = {n: fs.Plan(n, cap // n) for n in lengths}
+    fifo_arena = torch.empty(cap, dtype=torch.complex64, device="cuda")
+    budget_bytes = 200 * 10 ** 9
+    max_launch = 1 << 31                                   # bounds the two-pass scratch
+    arena_samples = (budget_bytes - max_launch * 8) // 8
+    ex = GpuExecutor(arena_samples)
+    # saturation of the plain path: every job queued at t = 0
+    sat_jobs = job_states(1e9, min(args.jobs, 300), 99)
+    st_sat = serve_fifo(sat_jobs, plans, fifo_arena)
+    lam_sat = st_sat["jobs_per_s"]
+    rows = []
+    for k, frac in enumerate(float(r) for r in args.rates.split(",")):
+        lam = frac * lam_sat
+        jobs_c = job_states(lam, args.jobs, 10 + k)
+        jobs_f = [JobState(j.index, j.arrival_s, j.seg_len, j.n_seg, j.host_in, j.host_out)
+                  for j in jobs_c]
+        ex.t0 = time.perf_counter()
+        ex.launches.clear()
+        sc = serve(jobs_c, ex, arena_samples, max_launch_samples=max_launch)
+        sf = serve_fifo(jobs_f, plans, fifo_arena)
+        rows.append({"rate_frac": frac, "rate_jobs_per_s": round(lam, 2),
+                     "continuous": {key: round(sc[key], 3) for key in
+                                    ("jobs_per_s", "p50_ms", "p99_ms", "mean_ms")} |
+                     {"launches": sc["launches"], "GB/s_payload":
+                      round(sc["samples_per_s"] * 8 / 1e9, 2)},
+                     "plain_fifo": {key: round(sf[key], 3) for key in
+                                    ("jobs_per_s", "p50_ms", "p99_ms", "mean_ms")}})
+        print(json.dumps({"progress": rows[-1]}), flush=True)
+    for p in plans.values():
+        p.close()
+    print(json.dumps({"workload": "serving", "jobs_per_rate": args.jobs,
+                      "plain_saturation_jobs_per_s": round(lam_sat, 2),
+                      "hbm_budget_bytes": budget_bytes, "pool_fill_s": round(t_pool, 2),
+                      "rates": rows}), flush=True)
+    return 0
+
+
+def run(args):
+    return {"small": small, "uneven": uneven, "streamed": streamed,
+            "serving": serving}[args.workload](args)

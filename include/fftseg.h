@@ -166,6 +166,120 @@ int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
                            void *const *host_out, int n_out, int n_slots,
                            fft_stream_stats_t *stats);
 
+/* ------------------------------------------------------------------------
+ * Uneven batches: one persistent launch over a work list (Sec. III batches
+ * the segments of a block into one plan; here segments of several lengths,
+ * at any offsets, share one kernel launch).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t in_off;      /* sample offset (not bytes) of the segment in in_base */
+    uint64_t out_off;     /* sample offset of its spectrum in out_base          */
+    uint32_t segment_len; /* a length fft_worklist_supported() accepts          */
+    uint32_t job;         /* caller's tag; not used by the library              */
+} fft_work_t;
+
+typedef struct fftseg_worklist *fft_worklist_t;
+
+/* 1 if segment_len has a work-list routine (256, 1000, 1024, 1536, 4096,
+ * 6000 in one pass; 16384, 65536 and 2^20 in two passes), else 0. */
+int fft_worklist_supported(uint32_t segment_len);
+
+/* Compile n entries into workgroup tasks: segments are grouped by length,
+ * packed S per tile for short lengths, split into column/row tiles for the
+ * two-pass lengths; the task list, per-length twiddle tables, counters and
+ * the two-pass scratch are uploaded once.  Output ranges must not overlap
+ * (FFT_ERR_OVERLAP); an unsupported length gives FFT_ERR_UNSUPPORTED_LENGTH.
+ * n may be 0 (an empty list to fill later with fft_worklist_reset).  All
+ * entry checks run before any device work.  NULL on error. */
+fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direction);
+
+/* Replace the entries of an existing work list (same rules as create),
+ * keeping its twiddle tables and device arrays (grown, after a device-wide
+ * synchronisation, only when too small).  The new task list is uploaded
+ * from pinned staging on `stream`, so it is ordered after earlier launches
+ * and before later ones on that stream.  For continuous batching: one work
+ * list is re-filled with whatever segments are ready. */
+int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, void *stream);
+
+/* Run every entry: one counter-clearing kernel and one persistent kernel
+ * whose workgroups claim tasks through an atomic cursor.  in_base and
+ * out_base are device pointers; every entry's range must lie in its
+ * buffer's allocation (FFT_ERR_BOUNDS).  in_base == out_base is allowed
+ * when each entry's output range either equals its input range or overlaps
+ * no input range (FFT_ERR_OVERLAP otherwise).  Asynchronous on stream. */
+int fft_exec_worklist(fft_worklist_t wl, const void *in_base, void *out_base, void *stream);
+
+/* Same work, launched as a hipGraph captured on first use (and re-captured
+ * when in_base/out_base change). */
+int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_base,
+                            void *stream);
+
+/* Synchronise `stream` and report whether the last run on it completed:
+ * FFT_ERR_TIMEOUT if a second-pass tile gave up waiting for its first pass
+ * (its outputs are then not written). */
+int fft_worklist_status(fft_worklist_t wl, void *stream);
+
+/* JSON summary (items, tasks, per-length counts, scratch bytes, grid). */
+int fft_worklist_describe(fft_worklist_t wl, char *buf, size_t len);
+
+/* Synchronise the device, then free the work list.  NULL is a no-op. */
+int fft_worklist_destroy(fft_worklist_t wl);
+
+/* ------------------------------------------------------------------------
+ * HIP graphs.
+ * ------------------------------------------------------------------------ */
+
+/* fft_exec_segments through a hipGraph: the plan's launch sequence for
+ * (in, out) is captured on the first call and replayed afterwards
+ * (re-captured when in or out change).  Same checks as fft_exec_segments. */
+int fft_exec_segments_graph(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Autotuning and kernel variants.
+ * ------------------------------------------------------------------------ */
+
+/* Time every compiled single-pass variant of segment_len (radix order,
+ * threads per segment, segments per workgroup, LDS padding, streamed or
+ * cached global access) at persistent-grid sizes {0, 4, 8, 16, 32, 64}
+ * resident workgroup waves per CU (two-pass lengths: every column-tile x
+ * row-tile variant of the chosen split, columns/rows per workgroup, tile
+ * order, streamed access, at each grid size), on
+ * device buffers of batch segments it allocates and frees.  The fastest
+ * choice goes into the process-wide tuning table used by later plans and,
+ * if path != NULL, is merged into that JSON cache file.  Returns the number
+ * of configurations timed (negative status on error); *best_us (may be
+ * NULL) receives the winner's time per exec in microseconds. */
+int fft_autotune(size_t segment_len, size_t batch, int direction, const char *path,
+                 double *best_us);
+
+/* Load a cache written by fft_autotune for this device's architecture;
+ * entries naming variants this build lacks are skipped.  Returns the number
+ * of entries loaded. */
+int fft_tune_load(const char *path);
+
+/* Forget every tuned choice (plans use the built-in defaults again). */
+int fft_tune_clear(void);
+
+/* Number of single-pass kernel variants compiled in for length n. */
+int fft_variant_count(size_t n);
+
+/* fft_plan_create, forcing single-pass variant `variant` (0 = default). */
+fft_plan_t fft_plan_create_variant(size_t segment_len, size_t batch, int direction,
+                                   int variant);
+
+/* For a two-pass length: the split N = n1 * n2 the planner uses and the
+ * number of compiled column-tile and row-tile variants for it.  Returns 1,
+ * or 0 if n is not a two-pass length (outputs set to 0). */
+int fft_split_info(size_t n, size_t *n1, size_t *n2, int *n_column_variants,
+                   int *n_row_variants);
+
+/* fft_plan_create for a two-pass length, forcing its column-tile and
+ * row-tile variants.  NULL (FFT_ERR_INVALID_ARG) if n is not two-pass or a
+ * variant does not exist. */
+fft_plan_t fft_plan_create_split(size_t segment_len, size_t batch, int direction,
+                                 int column_variant, int row_variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,12 @@ FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
 DRAIN_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
                             ctypes.c_void_p, ctypes.c_uint64)
 
+class WorkItem(ctypes.Structure):
+    """fft_work_t: sample offsets of one segment and of its spectrum."""
+    _fields_ = [("in_off", ctypes.c_uint64), ("out_off", ctypes.c_uint64),
+                ("segment_len", ctypes.c_uint32), ("job", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -91,6 +97,9 @@ def lib():
     _sig(L, "fft_plan_create", vp, [sz, sz, i32])
     _sig(L, "fft_plan_create_variant", vp, [sz, sz, i32, i32])
     _sig(L, "fft_variant_count", i32, [sz])
+    _sig(L, "fft_split_info", i32, [sz, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32)])
+    _sig(L, "fft_plan_create_split", vp, [sz, sz, i32, i32, i32])
     _sig(L, "fft_exec_segments", i32, [vp, vp, vp, vp])
     _sig(L, "fft_exec_segments_n", i32, [vp, vp, vp, sz, vp])
     _sig(L, "fft_plan_destroy", i32, [vp])
@@ -104,6 +113,19 @@ def lib():
     _sig(L, "fft_exec_stream_pinned", i32, [vp, u64, ctypes.POINTER(vp), i32,
                                             ctypes.POINTER(vp), i32, i32,
                                             ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_worklist_supported", i32, [ctypes.c_uint32])
+    _sig(L, "fft_worklist_create", vp, [ctypes.POINTER(WorkItem), sz, i32])
+    _sig(L, "fft_worklist_reset", i32, [vp, ctypes.POINTER(WorkItem), sz, vp])
+    _sig(L, "fft_exec_worklist", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_exec_worklist_graph", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_worklist_status", i32, [vp, vp])
+    _sig(L, "fft_worklist_describe", i32, [vp, ctypes.c_char_p, sz])
+    _sig(L, "fft_worklist_destroy", i32, [vp])
+    _sig(L, "fft_exec_segments_graph", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_autotune", i32, [sz, sz, i32, ctypes.c_char_p,
+                                  ctypes.POINTER(ctypes.c_double)])
+    _sig(L, "fft_tune_load", i32, [ctypes.c_char_p])
+    _sig(L, "fft_tune_clear", i32, [])
     _lib = L
     return L
 
@@ -128,6 +150,15 @@ def factorize(n: int) -> List[int]:
 def variant_count(n: int) -> int:
     """Single-pass kernel variants compiled in for length n."""
     return int(lib().fft_variant_count(n))
+
+
+def split_info(n: int):
+    """(n1, n2, column variants, row variants) of a two-pass length, or None."""
+    n1, n2 = ctypes.c_size_t(), ctypes.c_size_t()
+    c, r = ctypes.c_int(), ctypes.c_int()
+    ok = lib().fft_split_info(n, ctypes.byref(n1), ctypes.byref(n2), ctypes.byref(c),
+                              ctypes.byref(r))
+    return (n1.value, n2.value, c.value, r.value) if ok == 1 else None
 
 
 def _stream_handle(stream) -> int:
@@ -162,9 +193,12 @@ class Plan:
     """
 
     def __init__(self, segment_len: int, batch: int, direction: int = FORWARD,
-                 variant: Optional[int] = None):
+                 variant: Optional[int] = None, split_variants=None):
         L = lib()
-        if variant is None:
+        if split_variants is not None:
+            h = L.fft_plan_create_split(segment_len, batch, direction, split_variants[0],
+                                        split_variants[1])
+        elif variant is None:
             h = L.fft_plan_create(segment_len, batch, direction)
         else:
             h = L.fft_plan_create_variant(segment_len, batch, direction, variant)
@@ -189,6 +223,10 @@ class Plan:
         else:
             _check(lib().fft_exec_segments_n(self.handle, in_ptr, out_ptr, batch,
                                              stream))
+
+    def exec_graph_ptr(self, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+        """fft_exec_segments through a captured hipGraph."""
+        _check(lib().fft_exec_segments_graph(self.handle, in_ptr, out_ptr, stream))
 
     def exec(self, x, out=None, stream=None, batch: Optional[int] = None):
         """Transform torch complex64 GPU tensors; returns ``out``."""
@@ -279,3 +317,113 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class WorkList:
+    """Segments of uneven length at arbitrary sample offsets, run by one
+    persistent kernel launch.  ``entries`` is a sequence of
+    (in_off, out_off, segment_len[, job]) in samples, or a numpy structured
+    array with those fields."""
+
+    @staticmethod
+    def _items(entries):
+        import numpy as np
+        if isinstance(entries, np.ndarray) and entries.dtype.names:
+            arr = np.ascontiguousarray(entries)
+            n = len(arr)
+            items = (WorkItem * max(n, 1))()
+            buf = np.frombuffer(items, dtype=np.dtype([("in_off", "<u8"), ("out_off", "<u8"),
+                                                       ("segment_len", "<u4"), ("job", "<u4")]))[:n]
+            for f in ("in_off", "out_off", "segment_len"):
+                buf[f] = arr[f]
+            buf["job"] = arr["job"] if "job" in arr.dtype.names else 0
+        else:
+            entries = list(entries)
+            n = len(entries)
+            items = (WorkItem * max(n, 1))()
+            for i, e in enumerate(entries):
+                items[i].in_off, items[i].out_off, items[i].segment_len = e[0], e[1], e[2]
+                items[i].job = e[3] if len(e) > 3 else 0
+        return items, n
+
+    def __init__(self, entries=(), direction: int = FORWARD):
+        items, n = self._items(entries)
+        L = lib()
+        h = L.fft_worklist_create(items, n, direction)
+        if not h:
+            raise FFTError(L.fft_last_status(), last_error())
+        self._h = h
+        self.n_items = n
+        self.direction = direction
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("work list is destroyed")
+        return self._h
+
+    def reset(self, entries, stream=None) -> None:
+        """Replace the entries (upload ordered on ``stream``)."""
+        items, n = self._items(entries)
+        _check(lib().fft_worklist_reset(self.handle, items, n, _stream_handle(stream)))
+        self.n_items = n
+
+    def exec_ptr(self, in_base: int, out_base: int, stream: int = 0, graph: bool = False):
+        f = lib().fft_exec_worklist_graph if graph else lib().fft_exec_worklist
+        _check(f(self.handle, in_base, out_base, stream))
+
+    def exec(self, x, out, stream=None, graph: bool = False):
+        """Run on torch complex64 GPU tensors holding every entry's range."""
+        ip = _tensor_ptr(x, 0, "x")
+        op = _tensor_ptr(out, 0, "out")
+        self.exec_ptr(ip, op, _stream_handle(stream), graph)
+        return out
+
+    def status(self, stream=None) -> None:
+        """Synchronise and raise FFTError if a second-pass wait gave up."""
+        _check(lib().fft_worklist_status(self.handle, _stream_handle(stream)))
+
+    def describe(self) -> dict:
+        L = lib()
+        need = _check(L.fft_worklist_describe(self.handle, None, 0))
+        buf = ctypes.create_string_buffer(need + 1)
+        _check(L.fft_worklist_describe(self.handle, buf, need + 1))
+        return json.loads(buf.value.decode())
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft_worklist_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def worklist_supported(n: int) -> bool:
+    return bool(lib().fft_worklist_supported(n))
+
+
+def autotune(segment_len: int, batch: int, direction: int = FORWARD,
+             path: Optional[str] = None):
+    """Time every variant x grid size; returns (configurations timed, best us)."""
+    best = ctypes.c_double(0.0)
+    k = _check(lib().fft_autotune(segment_len, batch, direction,
+                                  path.encode() if path else None, ctypes.byref(best)))
+    return k, best.value
+
+
+def tune_load(path: str) -> int:
+    return _check(lib().fft_tune_load(path.encode()))
+
+
+def tune_clear() -> None:
+    _check(lib().fft_tune_clear())

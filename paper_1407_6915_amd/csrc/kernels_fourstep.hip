@@ -6,10 +6,14 @@
 namespace fftseg {
 namespace {
 
-template <int M, int T, int C, int PS, int... Rs>
+// flag bits: streamed global access, twiddles reloaded per tile,
+// XCD-aware tile order
+constexpr int kNT = 1, kNoHoist = 2, kXcd = 4;
+
+template <int M, int T, int C, int PS, int F, int... Rs>
 struct ColInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
-    using Pol = ColumnPolicy<Sh, C, PS>;
+    using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, (F & kNoHoist) == 0, (F & kXcd) != 0>;
     static void launch(int dir, const void *in, void *ybuf, const void *tw,
                        const void *tl, const void *th, int sh, int n2,
                        uint64_t batch, unsigned grid, hipStream_t s)
@@ -24,10 +28,12 @@ struct ColInst {
                                (const c32 *)in, (c32 *)ybuf, (const c32 *)tw,
                                (const c32 *)tl, (const c32 *)th, sh, n2, batch);
     }
-    static ColumnDesc desc()
+    static ColumnDesc desc(int variant)
     {
         ColumnDesc d{};
         d.n1 = M;
+        d.variant = variant;
+        d.flags = F;
         d.cols = C;
         d.threads = T;
         d.lds_bytes = Pol::kLdsElems * (int)sizeof(c32);
@@ -42,10 +48,10 @@ struct ColInst {
     }
 };
 
-template <int M, int T, int C, int PS, int... Rs>
+template <int M, int T, int C, int PS, int F, int... Rs>
 struct RowInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
-    using Pol = RowPolicy<Sh, C, PS>;
+    using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, (F & kNoHoist) == 0, (F & kXcd) != 0>;
     static void launch(int dir, const void *ybuf, void *out, const void *tw, int n1,
                        uint64_t batch, unsigned grid, hipStream_t s)
     {
@@ -57,10 +63,12 @@ struct RowInst {
             hipLaunchKernelGGL((four_step_rows_kernel<Sh, Pol, 1>), g, b, 0, s,
                                (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch);
     }
-    static RowDesc desc()
+    static RowDesc desc(int variant)
     {
         RowDesc d{};
         d.n2 = M;
+        d.variant = variant;
+        d.flags = F;
         d.rows = C;
         d.threads = T;
         d.lds_bytes = Pol::kLdsElems * (int)sizeof(c32);
@@ -75,21 +83,42 @@ struct RowInst {
     }
 };
 
-//                          M     T    C  PS  radices
+// Variant 0 of each length is the default; the tuner tries the others.
+//                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
-    ColInst<128, 8, 16, 4, 16, 8>::desc(),
-    ColInst<256, 16, 16, 4, 16, 16>::desc(),
-    ColInst<512, 64, 8, 4, 8, 8, 8>::desc(),
-    ColInst<1024, 64, 8, 4, 16, 16, 4>::desc(),
-    ColInst<2048, 128, 8, 4, 16, 16, 8>::desc(),
+    ColInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
+    ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
+    ColInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
+    ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
+    ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
+    ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
+    ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
+    ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
+    ColInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
+    ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
+    ColInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
+    ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
+    ColInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
+    ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
 };
 
 const RowDesc kRows[] = {
-    RowInst<128, 8, 16, 4, 16, 8>::desc(),
-    RowInst<256, 16, 16, 4, 16, 16>::desc(),
-    RowInst<512, 64, 8, 4, 8, 8, 8>::desc(),
-    RowInst<1024, 64, 8, 4, 16, 16, 4>::desc(),
-    RowInst<2048, 128, 8, 4, 16, 16, 8>::desc(),
+    RowInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
+    RowInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
+    RowInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
+    RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
+    RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
+    RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
+    RowInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
+    RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
+    RowInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
+    RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
+    RowInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
+    RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
+    RowInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
+    RowInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
+    RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
 };
 
 template <int R>

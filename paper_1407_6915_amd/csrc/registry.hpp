@@ -23,6 +23,9 @@ struct SinglePassDesc {
     int threads;        // threads per segment (T)
     int segs_per_wg;    // segments per workgroup (S)
     int pad_shift;      // one LDS pad element every 2^pad_shift (0: none)
+    int nontemporal;    // streamed (non-temporal) global loads and stores
+    int hoist;          // twiddles may stay in registers across segments
+    int grid_mult;      // default persistent grid: resident waves of workgroups
     int lds_bytes;
     int nrad;
     int radices[kMaxRadices];
@@ -32,7 +35,7 @@ struct SinglePassDesc {
 
 // Four-step pass A: N1-point column transforms, C columns per workgroup.
 struct ColumnDesc {
-    int n1, cols, threads, lds_bytes, nrad;
+    int n1, variant, cols, threads, lds_bytes, flags, nrad;
     int radices[kMaxRadices];
     col_launch_fn launch;
     const void *kernel[2];
@@ -40,7 +43,7 @@ struct ColumnDesc {
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.
 struct RowDesc {
-    int n2, rows, threads, lds_bytes, nrad;
+    int n2, variant, rows, threads, lds_bytes, flags, nrad;
     int radices[kMaxRadices];
     row_launch_fn launch;
     const void *kernel[2];

@@ -133,9 +133,9 @@ hipError_t upload(const std::vector<c32> &h, void **d)
     return e;
 }
 
-// the tuning table: preferred single-pass variant per length
+// the tuning table: preferred single-pass variant and grid per length
 std::mutex g_tune_mu;
-std::vector<std::pair<uint64_t, int>> g_tuned;
+std::vector<TunedChoice> g_tuned;
 
 }  // namespace
 
@@ -143,20 +143,40 @@ int tuned_variant(uint64_t n)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &p : g_tuned)
-        if (p.first == n)
-            return p.second;
+        if (p.n == n)
+            return p.variant;
     return -1;
 }
 
-void set_tuned_variant(uint64_t n, int variant)
+int tuned_grid_mult(uint64_t n, int variant, int fallback)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &p : g_tuned)
-        if (p.first == n) {
-            p.second = variant;
+        if (p.n == n && p.variant == variant)
+            return p.grid_mult;
+    return fallback;
+}
+
+void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.n == n && p.variant < 0) {
+            *col_variant = p.col_variant;
+            *row_variant = p.row_variant;
             return;
         }
-    g_tuned.emplace_back(n, variant);
+}
+
+void set_tuned(const TunedChoice &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.n == c.n) {
+            p = c;
+            return;
+        }
+    g_tuned.push_back(c);
 }
 
 void clear_tuned()
@@ -165,7 +185,7 @@ void clear_tuned()
     g_tuned.clear();
 }
 
-std::vector<std::pair<uint64_t, int>> tuned_snapshot()
+std::vector<TunedChoice> tuned_snapshot()
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     return g_tuned;
@@ -190,8 +210,11 @@ int variant_count(uint64_t n)
     return k;
 }
 
-// best four-step split n = n1 * n2 with compiled column and row tiles
-bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row)
+// best four-step split n = n1 * n2 with compiled column and row tiles;
+// the split is chosen on the default tiles, then the requested variants of
+// those lengths are used (default where a variant does not exist)
+bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,
+                int row_variant)
 {
     int nc = 0, nr = 0;
     const ColumnDesc *ct = column_table(&nc);
@@ -200,13 +223,11 @@ bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row)
     *col = nullptr;
     *row = nullptr;
     for (int i = 0; i < nc; ++i) {
-        if (n % (uint64_t)ct[i].n1)
+        if (ct[i].variant != 0 || n % (uint64_t)ct[i].n1)
             continue;
         const uint64_t n2 = n / (uint64_t)ct[i].n1;
         for (int j = 0; j < nr; ++j) {
-            if ((uint64_t)rt[j].n2 != n2)
-                continue;
-            if (n2 % (uint64_t)ct[i].cols || (uint64_t)ct[i].n1 % (uint64_t)rt[j].rows)
+            if (rt[j].variant != 0 || (uint64_t)rt[j].n2 != n2)
                 continue;
             // prefer balanced splits, then the smaller column length
             const double score =
@@ -219,15 +240,79 @@ bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row)
             }
         }
     }
-    return *col != nullptr;
+    if (!*col)
+        return false;
+    const uint64_t n1 = (uint64_t)(*col)->n1, n2 = n / n1;
+    auto fits = [&](const ColumnDesc &c, const RowDesc &r) {
+        return n2 % (uint64_t)c.cols == 0 && n1 % (uint64_t)r.rows == 0;
+    };
+    for (int i = 0; i < nc; ++i)
+        if ((uint64_t)ct[i].n1 == n1 && ct[i].variant == col_variant && fits(ct[i], **row))
+            *col = &ct[i];
+    for (int j = 0; j < nr; ++j)
+        if ((uint64_t)rt[j].n2 == n2 && rt[j].variant == row_variant && fits(**col, rt[j]))
+            *row = &rt[j];
+    return fits(**col, **row);
 }
+
+int split_variant_counts(uint64_t n, int *ncol, int *nrow)
+{
+    const ColumnDesc *c = nullptr;
+    const RowDesc *r = nullptr;
+    *ncol = *nrow = 0;
+    if (!find_split(n, &c, &r, 0, 0))
+        return 0;
+    int nc = 0, nr = 0;
+    const ColumnDesc *ct = column_table(&nc);
+    const RowDesc *rt = row_table(&nr);
+    for (int i = 0; i < nc; ++i)
+        *ncol += ct[i].n1 == c->n1;
+    for (int j = 0; j < nr; ++j)
+        *nrow += rt[j].n2 == r->n2;
+    return 1;
+}
+
+// CU count per device and resident workgroups per CU per kernel, cached:
+// both are fixed for the life of the process and the queries are slow.
+namespace {
+std::mutex g_occ_mu;
+std::vector<std::pair<int, int>> g_cus;                      // (device, CUs)
+std::vector<std::pair<std::pair<const void *, int>, int>> g_occ;  // ((kernel, dev), per CU)
+}  // namespace
 
 static int device_cus(int dev)
 {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
-        return 256;
-    return p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    for (auto &c : g_cus)
+        if (c.first == dev)
+            return c.second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0) {
+        (void)hipGetLastError();
+        n = 256;
+    }
+    g_cus.emplace_back(dev, n);
+    return n;
+}
+
+static int resident_per_cu(const void *kernel, int threads, int dev)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        for (auto &o : g_occ)
+            if (o.first.first == kernel && o.first.second == dev)
+                return o.second;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    g_occ.push_back({{kernel, dev}, per_cu});
+    return per_cu;
 }
 
 unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
@@ -235,29 +320,29 @@ unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev
 {
     uint64_t g = work_groups;
     if (grid_mult > 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
-                hipSuccess ||
-            per_cu <= 0) {
-            (void)hipGetLastError();
-            per_cu = 1;
-        }
-        const uint64_t cap = (uint64_t)per_cu * (uint64_t)device_cus(dev) * (uint64_t)grid_mult;
+        const uint64_t cap = (uint64_t)resident_per_cu(kernel, threads, dev) *
+                             (uint64_t)device_cus(dev) * (uint64_t)grid_mult;
         g = std::min<uint64_t>(g, cap);
     }
     g = std::min<uint64_t>(g, 0x7fffffffull);
     return (unsigned)std::max<uint64_t>(g, 1);
 }
 
+// Persistent grid: this many resident workgroup waves per CU (each
+// workgroup walks tiles with a grid-stride loop, so twiddles loaded once
+// stay in registers); FFTSEG_GRID_MULT=0 gives one workgroup per tile.
+constexpr int kDefaultGridMult = 8;
+
 int env_grid_mult()
 {
     const char *e = getenv("FFTSEG_GRID_MULT");
-    return e ? atoi(e) : 0;
+    return e ? atoi(e) : kDefaultGridMult;
 }
 
 // ---------------------------------------------------------------------------
 // plan construction
-int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant)
+int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
+               int forced_split_variants)
 {
     p->n = n;
     p->batch = batch;
@@ -283,6 +368,8 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant)
                          (unsigned long long)n, forced_variant);
     if (p->sp) {
         p->kind = Plan::SINGLE;
+        if (!getenv("FFTSEG_GRID_MULT"))
+            p->grid_mult = tuned_grid_mult(n, p->sp->variant, p->sp->grid_mult);
         if ((e = upload(root_table(n), &p->tw)) != hipSuccess)
             return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
                                             : hip_error(e, "twiddle upload");
@@ -302,7 +389,16 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant)
                                             : hip_error(e, "twiddle upload");
     }
     p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / n));
-    if (find_split(n, &p->col, &p->row)) {
+    if (!getenv("FFTSEG_GRID_MULT"))
+        p->grid_mult = tuned_grid_mult(n, -1, p->grid_mult);
+    int cv = 0, rv = 0;
+    if (forced_split_variants >= 0) {
+        cv = forced_split_variants & 0xff;
+        rv = (forced_split_variants >> 8) & 0xff;
+    } else {
+        tuned_split_variants(n, &cv, &rv);
+    }
+    if (find_split(n, &p->col, &p->row, cv, rv)) {
         p->kind = Plan::FOURSTEP;
         p->n1 = (uint64_t)p->col->n1;
         p->n2 = (uint64_t)p->row->n2;
@@ -337,6 +433,11 @@ void plan_free(Plan *p)
         (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph)
         (void)hipGraphDestroy(p->graph);
+    if (p->capture_stream)
+        (void)hipStreamDestroy(p->capture_stream);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->capture_stream = nullptr;
     p->tw = p->tw2 = p->tl = p->th = p->scratch = nullptr;
 }
 
@@ -485,22 +586,25 @@ int plan_describe(const Plan *p, std::string &js)
         snprintf(buf, sizeof buf,
                  "{\"kind\":\"single_pass\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
                  "\"variant\":%d,\"radices\":%s,\"threads_per_segment\":%d,"
-                 "\"segments_per_workgroup\":%d,\"lds_pad_shift\":%d,\"lds_bytes\":%d,"
-                 "\"scratch_bytes\":0}",
+                 "\"segments_per_workgroup\":%d,\"lds_pad_shift\":%d,\"nontemporal\":%d,"
+                 "\"lds_bytes\":%d,\"grid_mult\":%d,\"scratch_bytes\":0}",
                  (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
                  p->sp->variant, rad(p->sp->radices, p->sp->nrad).c_str(), p->sp->threads,
-                 p->sp->segs_per_wg, p->sp->pad_shift, p->sp->lds_bytes);
+                 p->sp->segs_per_wg, p->sp->pad_shift, p->sp->nontemporal,
+                 p->sp->lds_bytes, p->grid_mult);
         break;
     case Plan::FOURSTEP:
         snprintf(buf, sizeof buf,
                  "{\"kind\":\"four_step\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
                  "\"n1\":%llu,\"n2\":%llu,\"radices_n1\":%s,\"radices_n2\":%s,"
                  "\"columns_per_workgroup\":%d,\"rows_per_workgroup\":%d,"
+                 "\"column_variant\":%d,\"row_variant\":%d,\"grid_mult\":%d,"
                  "\"lds_bytes\":[%d,%d],\"sub_batch\":%llu,\"scratch_bytes\":%zu}",
                  (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
                  (unsigned long long)p->n1, (unsigned long long)p->n2,
                  rad(p->col->radices, p->col->nrad).c_str(),
                  rad(p->row->radices, p->row->nrad).c_str(), p->col->cols, p->row->rows,
+                 p->col->variant, p->row->variant, p->grid_mult,
                  p->col->lds_bytes, p->row->lds_bytes, (unsigned long long)p->sub_batch,
                  p->scratch_bytes);
         break;
@@ -581,12 +685,13 @@ using namespace fftseg;
         return ret;                                                                \
     }
 
-static fft_plan_t create_impl(size_t segment_len, size_t batch, int direction, int variant)
+static fft_plan_t create_impl(size_t segment_len, size_t batch, int direction, int variant,
+                              int split = -1)
 {
     if (validate_create(segment_len, batch, direction) != FFT_OK)
         return nullptr;
     Plan *p = new Plan();
-    if (plan_build(p, segment_len, batch, direction, variant) != FFT_OK) {
+    if (plan_build(p, segment_len, batch, direction, variant, split) != FFT_OK) {
         const int st = last_status();
         std::string msg = last_message();
         plan_free(p);
@@ -613,6 +718,48 @@ extern "C" fft_plan_t fft_plan_create_variant(size_t segment_len, size_t batch,
         return nullptr;
     }
     return create_impl(segment_len, batch, direction, variant);
+    FFT_GUARD_END(nullptr)
+}
+
+extern "C" int fft_split_info(size_t n, size_t *n1, size_t *n2, int *ncol, int *nrow)
+{
+    FFT_GUARD_BEGIN
+    int c = 0, r = 0;
+    const ColumnDesc *cd = nullptr;
+    const RowDesc *rd = nullptr;
+    const bool two = n > 0 && variant_count(n) == 0 && find_split(n, &cd, &rd, 0, 0);
+    if (two)
+        split_variant_counts(n, &c, &r);
+    if (n1)
+        *n1 = two ? (size_t)cd->n1 : 0;
+    if (n2)
+        *n2 = two ? (size_t)rd->n2 : 0;
+    if (ncol)
+        *ncol = c;
+    if (nrow)
+        *nrow = r;
+    set_ok();
+    return two ? 1 : 0;
+    FFT_GUARD_END(FFT_ERR_INVALID_ARG)
+}
+
+extern "C" fft_plan_t fft_plan_create_split(size_t segment_len, size_t batch, int direction,
+                                            int column_variant, int row_variant)
+{
+    FFT_GUARD_BEGIN
+    int c = 0, r = 0;
+    if (validate_create(segment_len, batch, direction) != FFT_OK)
+        return nullptr;
+    if (variant_count(segment_len) != 0 || !split_variant_counts(segment_len, &c, &r)) {
+        set_error(FFT_ERR_INVALID_ARG, "length %zu is not a two-pass length", segment_len);
+        return nullptr;
+    }
+    if (column_variant < 0 || column_variant >= c || row_variant < 0 || row_variant >= r) {
+        set_error(FFT_ERR_INVALID_ARG, "tile variants (%d, %d) outside [0, %d) x [0, %d)",
+                  column_variant, row_variant, c, r);
+        return nullptr;
+    }
+    return create_impl(segment_len, batch, direction, -1, column_variant | (row_variant << 8));
     FFT_GUARD_END(nullptr)
 }
 

@@ -40,6 +40,7 @@ struct Plan {
     hipGraphExec_t graph_exec = nullptr;
     const void *graph_in = nullptr;
     void *graph_out = nullptr;
+    hipStream_t capture_stream = nullptr;
     void *stream_state = nullptr;  // pinned host ring of the streaming path
 };
 
@@ -52,12 +53,17 @@ const char *last_message();
 c32 root_forward(uint64_t m, uint64_t n);
 const SinglePassDesc *find_single(uint64_t n, int variant);
 int variant_count(uint64_t n);
-bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row);
+bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,
+                int row_variant);
+int split_variant_counts(uint64_t n, int *ncol, int *nrow);
 unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
                   int grid_mult);
 
 int validate_create(uint64_t n, uint64_t batch, int dir);
-int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant);
+// forced_variant: single-pass variant (-1: tuned/default); forced_split_variants:
+// column variant | row variant << 8 of a four-step plan (-1: tuned/default)
+int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
+               int forced_split_variants = -1);
 void plan_free(Plan *p);
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
 int plan_describe(const Plan *p, std::string &js);
@@ -66,9 +72,20 @@ int check_device_range(const void *ptr, uint64_t bytes, const char *name);
 
 void stream_state_free(Plan *p);
 
+struct TunedChoice {
+    uint64_t n;
+    int variant;      // single-pass variant, -1 for two-pass and fallback plans
+    int grid_mult;
+    double us;        // measured time per exec when tuned (0 if loaded without)
+    uint64_t batch;
+    int col_variant;  // two-pass plans: column and row tile variants
+    int row_variant;
+};
 int tuned_variant(uint64_t n);
-void set_tuned_variant(uint64_t n, int variant);
+int tuned_grid_mult(uint64_t n, int variant, int fallback);
+void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant);
+void set_tuned(const TunedChoice &c);
 void clear_tuned();
-std::vector<std::pair<uint64_t, int>> tuned_snapshot();
+std::vector<TunedChoice> tuned_snapshot();
 
 }  // namespace fftseg

@@ -42,6 +42,30 @@ struct Radices {
     }
 };
 
+// Global memory access: plain, or non-temporal (streamed data that is not
+// re-read soon, so it need not displace cached lines).
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ c32 gload(const c32 *p)
+{
+    if constexpr (NT) {
+        const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+        return c32{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void gstore(c32 *p, c32 v)
+{
+    if constexpr (NT) {
+        const f2v w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<f2v *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // Transform shape: length M, T threads per transform, radix list.
 template <int M_, int T_, class Rad_>
 struct Shape {
@@ -89,7 +113,10 @@ __device__ __forceinline__ void st_gather(c32 *v, int t, Get &&get)
 }
 
 // twiddle + R-point DFT of this thread's butterflies
-template <class St, class Sh, int L, int D>
+// (Hoist = false keeps the twiddle loads inside a persistent loop: the
+// index is made opaque to the compiler so the loads are not lifted out and
+// held in registers across segments.)
+template <class St, class Sh, int L, int D, bool Hoist = true>
 __device__ __forceinline__ void st_compute(c32 *v, int t,
                                            const c32 *__restrict__ tw)
 {
@@ -98,7 +125,9 @@ __device__ __forceinline__ void st_compute(c32 *v, int t,
         const int b = t + u * Sh::T;
         if (St::kFull || b < St::NB) {
             if constexpr (L > 1) {
-                const int k = b % L;
+                int k = b % L;
+                if constexpr (!Hoist)
+                    asm volatile("" : "+v"(k));
 #pragma unroll
                 for (int r = 1; r < St::R; ++r)
                     v[u * St::R + r] = twiddle<D>(
@@ -136,16 +165,21 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
     using St = Stage<Sh, I, L>;
     const int c = Pol::template col<I>(tid);
     const int t = Pol::template thr<I>(tid);
-    st_compute<St, Sh, L, D>(v, t, tw);
+    const bool act = Pol::active(tid);
+    if (act)
+        st_compute<St, Sh, L, D, Pol::kHoist>(v, t, tw);
     if constexpr (St::kLast) {
-        Pol::template store<St, D>(v, t, c, ctx);
+        if (act)
+            Pol::template store<St, D>(v, t, c, ctx);
     } else {
-        st_scatter<St, Sh, L>(v, t, [&](int i, c32 a) { lds[Pol::lds(c, i)] = a; });
+        if (act)
+            st_scatter<St, Sh, L>(v, t, [&](int i, c32 a) { lds[Pol::lds(c, i)] = a; });
         __syncthreads();
         using Nx = Stage<Sh, I + 1, L * St::R>;
         const int c2 = Pol::template col<I + 1>(tid);
         const int t2 = Pol::template thr<I + 1>(tid);
-        st_gather<Nx, Sh>(v, t2, [&](int i) { return lds[Pol::lds(c2, i)]; });
+        if (act)
+            st_gather<Nx, Sh>(v, t2, [&](int i) { return lds[Pol::lds(c2, i)]; });
         __syncthreads();
         tile_run<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, ctx);
     }
@@ -155,10 +189,16 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
 // Single pass: S whole segments per workgroup, each owned by T threads.
 //   lane mapping: segment slot = tid / T, thread t = tid % T (all stages);
 //   LDS: slot * SegStride + i + (i >> PS) (one pad element every 2^PS).
-template <class Sh, int S_, int PS_>
+// (Partial = the workgroup may have more threads than S*T; the extra
+// threads only take part in barriers.)
+template <class Sh, int S_, int PS_, bool NT_ = false, bool Hoist_ = true,
+          bool Partial_ = false>
 struct SinglePassPolicy {
     static constexpr int S = S_;
     static constexpr int PS = PS_;
+    static constexpr bool kNT = NT_;
+    static constexpr bool kHoist = Hoist_;
+    static constexpr bool kPartial = Partial_;
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kSegStride = pad(Sh::M - 1) + 1;
     static constexpr int kLdsElems = Sh::NS > 1 ? S * kSegStride : 1;
@@ -173,6 +213,10 @@ struct SinglePassPolicy {
     template <int I>
     static __device__ __forceinline__ int thr(int tid) { return S == 1 ? tid : tid % Sh::T; }
     static __device__ __forceinline__ int lds(int c, int i) { return c * kSegStride + pad(i); }
+    static __device__ __forceinline__ bool active(int tid)
+    {
+        return !kPartial || tid < kThreads;
+    }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int, const Ctx &ctx)
@@ -185,11 +229,26 @@ struct SinglePassPolicy {
             if (St::kFull || b < St::NB) {
 #pragma unroll
                 for (int r = 0; r < St::R; ++r)
-                    ctx.y[b + r * St::NB] = v[u * St::R + r];
+                    gstore<kNT>(ctx.y + b + r * St::NB, v[u * St::R + r]);
             }
         }
     }
 };
+
+// One tile of up to S whole segments: slot c of the tile reads x_c and
+// writes y_c (valid_c false for an empty slot).
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
+                                            const c32 *x, c32 *y, bool valid)
+{
+    const int t = Pol::template thr<0>(tid);
+    typename Pol::Ctx ctx{y, valid && Pol::active(tid)};
+    c32 v[Sh::kMaxE];
+    using S0 = Stage<Sh, 0, 1>;
+    if (ctx.valid)
+        st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+}
 
 template <class Sh, class Pol, int D>
 __global__ void __launch_bounds__(Pol::kThreads)
@@ -199,20 +258,13 @@ __global__ void __launch_bounds__(Pol::kThreads)
     __shared__ c32 lds[Pol::kLdsElems];
     const int tid = threadIdx.x;
     const int slot = Pol::template col<0>(tid);
-    const int t = Pol::template thr<0>(tid);
     const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
     for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
         const uint64_t seg = g * Pol::S + slot;
-        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch};
-        const c32 *x = in + seg * Sh::M;
-        c32 v[Sh::kMaxE];
-        using S0 = Stage<Sh, 0, 1>;
-        if (ctx.valid)
-            st_gather<S0, Sh>(v, t, [&](int i) { return x[i]; });
-        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+        single_tile<Sh, Pol, D>(lds, tw, tid, in + seg * Sh::M, out + seg * Sh::M,
+                                seg < batch);
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // Four-step split N = N1 * N2 for segments longer than one LDS tile.
@@ -227,6 +279,21 @@ __global__ void __launch_bounds__(Pol::kThreads)
 // W_N^m (m = n2*k1 < N) is the product of two table entries
 // th[m >> sh] * tl[m & (2^sh - 1)], each evaluated in FP64 and rounded once.
 
+// Tile order of a persistent grid.  Workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup w on XCD w % 8); with Xcd the tiles of one
+// sweep are dealt so that the workgroups of one XCD take consecutive tiles,
+// so adjacent column blocks -- the two halves of the same cache lines --
+// are read through the same L2 at about the same time.
+template <bool Xcd>
+__device__ __forceinline__ uint64_t tile_of(uint64_t sweep_base, unsigned w, unsigned grid)
+{
+    if constexpr (Xcd) {
+        if ((grid & 7u) == 0)
+            return sweep_base + (uint64_t)(w & 7u) * (grid >> 3) + (w >> 3);
+    }
+    return sweep_base + w;
+}
+
 struct FourStepCtx {
     const c32 *x;   // pass A: segment input;     pass B: segment of Y
     c32 *y;         // pass A: segment of Y;      pass B: segment output
@@ -239,10 +306,14 @@ struct FourStepCtx {
 };
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
-template <class Sh, int C_, int PS_>
+template <class Sh, int C_, int PS_, bool NT_ = false, bool Hoist_ = true,
+          bool Xcd_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
+    static constexpr bool kNT = NT_;
+    static constexpr bool kHoist = Hoist_;
+    static constexpr bool kXcd = Xcd_;
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kLdsElems = (pad(Sh::M - 1) + 1) * C;
     static constexpr int kThreads = Sh::T * C;
@@ -252,6 +323,7 @@ struct ColumnPolicy {
     template <int I>
     static __device__ __forceinline__ int thr(int tid) { return tid / C; }
     static __device__ __forceinline__ int lds(int c, int i) { return pad(i) * C + c; }
+    static __device__ __forceinline__ bool active(int) { return true; }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
@@ -269,12 +341,31 @@ struct ColumnPolicy {
                     const unsigned k1 = (unsigned)(b + r * St::NB);
                     const unsigned m = n2 * k1;
                     const c32 w = cmul(ctx.th[m >> ctx.sh], ctx.tl[m & mask]);
-                    ctx.y[(size_t)k1 * ctx.n2 + n2] = twiddle<D>(v[u * St::R + r], w);
+                    gstore<kNT>(ctx.y + (size_t)k1 * ctx.n2 + n2,
+                                twiddle<D>(v[u * St::R + r], w));
                 }
             }
         }
     }
 };
+
+// One pass-A tile: columns first..first+C-1 of one segment (x: segment
+// input, y: the segment's Y buffer, n2 columns).
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw,
+                                            const c32 *__restrict__ tl,
+                                            const c32 *__restrict__ th, int sh, int tid,
+                                            const c32 *x, c32 *y, int first, int n2)
+{
+    FourStepCtx ctx{x, y, first, Sh::M, n2, tl, th, sh, true};
+    const int c = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    c32 v[Sh::kMaxE];
+    using S0 = Stage<Sh, 0, 1>;
+    const c32 *xc = x + first + c;
+    st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+}
 
 template <class Sh, class Pol, int D>
 __global__ void __launch_bounds__(Pol::kThreads)
@@ -283,32 +374,31 @@ __global__ void __launch_bounds__(Pol::kThreads)
                              int sh, int n2, uint64_t batch)
 {
     __shared__ c32 lds[Pol::kLdsElems];
-    const int tid = threadIdx.x;
-    const int c = Pol::template col<0>(tid);
-    const int t = Pol::template thr<0>(tid);
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        FourStepCtx ctx{in + seg * nseg, ybuf + seg * nseg, first, Sh::M, n2,
-                        tl, th, sh, true};
-        c32 v[Sh::kMaxE];
-        using S0 = Stage<Sh, 0, 1>;
-        const c32 *x = ctx.x + first + c;
-        st_gather<S0, Sh>(v, t, [&](int i) { return x[(size_t)i * n2]; });
-        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh, threadIdx.x, in + seg * nseg,
+                                ybuf + seg * nseg, first, n2);
     }
 }
 
 // Pass B: lanes row-major (c = tid / T, t = tid % T) up to the last stage,
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
-template <class Sh, int C_, int PS_>
+template <class Sh, int C_, int PS_, bool NT_ = false, bool Hoist_ = true,
+          bool Xcd_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
+    static constexpr bool kNT = NT_;
+    static constexpr bool kHoist = Hoist_;
+    static constexpr bool kXcd = Xcd_;
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kRow = (pad(Sh::M - 1) + 1) | 1;  // odd row stride
     static constexpr int kLdsElems = kRow * C;
@@ -325,6 +415,7 @@ struct RowPolicy {
         return (I + 1 == Sh::NS) ? tid / C : tid % Sh::T;
     }
     static __device__ __forceinline__ int lds(int c, int i) { return c * kRow + pad(i); }
+    static __device__ __forceinline__ bool active(int) { return true; }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
@@ -338,35 +429,46 @@ struct RowPolicy {
             if (St::kFull || b < St::NB) {
 #pragma unroll
                 for (int r = 0; r < St::R; ++r)
-                    y[(size_t)(b + r * St::NB) * ctx.n1] = v[u * St::R + r];
+                    gstore<kNT>(y + (size_t)(b + r * St::NB) * ctx.n1, v[u * St::R + r]);
             }
         }
     }
 };
+
+// One pass-B tile: rows first..first+C-1 of one segment's Y (y: Y of the
+// segment, x: segment output, n1 rows).
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
+                                         const c32 *y, c32 *x, int first, int n1)
+{
+    static_assert(Sh::NS > 1, "the row pass changes lane mapping through LDS");
+    FourStepCtx ctx{y, x, first, n1, Sh::M, nullptr, nullptr, 0, true};
+    const int c = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    c32 v[Sh::kMaxE];
+    using S0 = Stage<Sh, 0, 1>;
+    const c32 *yr = y + (size_t)(first + c) * Sh::M;
+    st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+}
 
 template <class Sh, class Pol, int D>
 __global__ void __launch_bounds__(Pol::kThreads)
     four_step_rows_kernel(const c32 *ybuf, c32 *out, const c32 *__restrict__ tw,
                           int n1, uint64_t batch)
 {
-    static_assert(Sh::NS > 1, "the row pass changes lane mapping through LDS");
     __shared__ c32 lds[Pol::kLdsElems];
-    const int tid = threadIdx.x;
-    const int c = Pol::template col<0>(tid);
-    const int t = Pol::template thr<0>(tid);
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n1;
     const uint64_t blocks = (uint64_t)(n1 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        FourStepCtx ctx{ybuf + seg * nseg, out + seg * nseg, first, n1, Sh::M,
-                        nullptr, nullptr, 0, true};
-        c32 v[Sh::kMaxE];
-        using S0 = Stage<Sh, 0, 1>;
-        const c32 *x = ctx.x + (size_t)(first + c) * Sh::M;
-        st_gather<S0, Sh>(v, t, [&](int i) { return x[i]; });
-        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+        row_tile<Sh, Pol, D>(lds, tw, threadIdx.x, ybuf + seg * nseg, out + seg * nseg,
+                             first, n1);
     }
 }
 

@@ -1,0 +1,837 @@
+// Uneven batches in one persistent launch (fft_worklist_*).
+//
+// The paper batches the fixed-length segments of one block into one plan
+// (Sec. III); here segments of different lengths, at arbitrary offsets, go
+// through ONE kernel launch.  The host compiles the entries into tasks,
+// each filling one 256-thread workgroup tile:
+//   single pass  up to S whole segments of one length (S = 16 for 256, ...)
+//   two pass     one column tile (pass A) or row tile (pass B) of a
+//                four-step segment (16384 = 128 x 128, 65536 = 256 x 256)
+// Workgroups claim tasks through an atomic cursor in list order: all pass-A
+// tiles first, then single-pass tasks (longest first), then pass-B tiles.
+// A pass-B tile waits until its segment's pass-A tiles have signalled a
+// per-segment counter.  Those tiles were claimed earlier by workgroups that
+// are running and never wait, so every wait ends; a bounded spin still
+// caps it and raises an error flag instead of hanging.
+#include "fftseg.h"
+#include "runtime.hpp"
+#include "tile.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace fftseg {
+namespace wl {
+
+enum Kind : uint32_t {
+    K256,
+    K1000,
+    K1024,
+    K1536,
+    K4096,
+    K6000,
+    K16384A,
+    K16384B,
+    K65536A,
+    K65536B,
+    K1MA,
+    K1MB,
+    KCOUNT
+};
+
+struct Item {          // one segment
+    uint64_t in_off;   // samples from in_base
+    uint64_t out_off;  // samples from out_base
+    uint64_t y_off;    // two-pass: samples from the scratch base
+};
+
+struct Task {
+    uint32_t kind;
+    uint32_t item;   // first item of the task (items sorted per task)
+    uint32_t count;  // single pass: segments in the tile
+    uint32_t tile;   // two pass: column/row block; counter index in dep
+    uint32_t dep;    // two pass: per-segment counter index
+    uint32_t pad[3];
+};
+
+struct Tables {      // per kind, device pointers
+    const c32 *tw;   // W_M of the tile transform
+    const c32 *tl, *th;
+    int sh;
+    int pad;
+};
+
+constexpr int kThreads = 256;
+
+// routine shapes
+using Sh256 = Shape<256, 16, Radices<16, 16>>;
+using P256 = SinglePassPolicy<Sh256, 16, 4, false, false, false>;
+using Sh1000 = Shape<1000, 100, Radices<10, 10, 10>>;
+using P1000 = SinglePassPolicy<Sh1000, 2, 4, false, false, true>;
+using Sh1024 = Shape<1024, 64, Radices<16, 16, 4>>;
+using P1024 = SinglePassPolicy<Sh1024, 4, 4, false, false, false>;
+using Sh1536 = Shape<1536, 96, Radices<16, 16, 6>>;
+using P1536 = SinglePassPolicy<Sh1536, 2, 4, false, false, true>;
+using Sh4096 = Shape<4096, 256, Radices<16, 16, 16>>;
+using P4096 = SinglePassPolicy<Sh4096, 1, 4, false, false, false>;
+using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
+using P6000 = SinglePassPolicy<Sh6000, 1, 4, false, false, false>;
+using Sh128 = Shape<128, 8, Radices<16, 8>>;
+using PCol128 = ColumnPolicy<Sh128, 32, 4, false, false>;
+using PRow128 = RowPolicy<Sh128, 32, 4, false, false>;
+using Sh256c = Shape<256, 16, Radices<16, 16>>;
+using PCol256 = ColumnPolicy<Sh256c, 16, 4, false, false>;
+using PRow256 = RowPolicy<Sh256c, 16, 4, false, false>;
+using Sh1k = Shape<1024, 64, Radices<16, 16, 4>>;
+using PCol1k = ColumnPolicy<Sh1k, 4, 4, false, false>;
+using PRow1k = RowPolicy<Sh1k, 4, 4, false, false>;
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kLdsElems =
+    cmax(cmax(cmax(P256::kLdsElems, P1000::kLdsElems), cmax(P1024::kLdsElems, P1536::kLdsElems)),
+         cmax(cmax(P4096::kLdsElems, P6000::kLdsElems),
+              cmax(cmax(cmax(PCol128::kLdsElems, PRow128::kLdsElems),
+                        cmax(PCol256::kLdsElems, PRow256::kLdsElems)),
+                   cmax(PCol1k::kLdsElems, PRow1k::kLdsElems))));
+
+static_assert(P256::kThreads <= kThreads && P1000::kThreads <= kThreads &&
+                  P1024::kThreads <= kThreads && P1536::kThreads <= kThreads &&
+                  P4096::kThreads <= kThreads && P6000::kThreads <= kThreads,
+              "single-pass routines must fit the workgroup");
+static_assert(PCol128::kThreads == kThreads && PRow128::kThreads == kThreads &&
+                  PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
+                  PCol1k::kThreads == kThreads && PRow1k::kThreads == kThreads,
+              "two-pass routines use the whole workgroup");
+
+// spin bound for a pass-B wait (~tens of ms, far above one tile's time)
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void run_single(c32 *lds, const Tables &tb, const Task &t,
+                                           const Item *__restrict__ items, const c32 *in,
+                                           c32 *out, int tid)
+{
+    const int slot = tid / Sh::T;
+    const bool valid = Pol::active(tid) && slot < (int)t.count;
+    const Item it = valid ? items[t.item + slot] : Item{0, 0, 0};
+    single_tile<Sh, Pol, D>(lds, tb.tw, tid, in + it.in_off, out + it.out_off, valid);
+}
+
+__device__ __forceinline__ void signal_done(uint32_t *counter, int tid)
+{
+    __threadfence();  // release this tile's stores device-wide
+    __syncthreads();
+    if (tid == 0)
+        atomicAdd(counter, 1u);
+}
+
+// wait until *counter >= target; returns false (and raises the error flag)
+// if the bound is hit
+__device__ __forceinline__ bool wait_for(uint32_t *counter, uint32_t target, uint32_t *err,
+                                         int tid, uint32_t *s_ok)
+{
+    if (tid == 0) {
+        uint32_t spins = 0, ok = 1;
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 1u);
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    const bool ok = *s_ok != 0;
+    __threadfence();  // acquire the producers' stores
+    return ok;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads)
+    worklist_kernel(const Task *__restrict__ tasks, uint32_t n_tasks,
+                    const Item *__restrict__ items, const Tables *__restrict__ tables,
+                    const c32 *in, c32 *out, c32 *ybuf, uint32_t *ctl)
+{
+    // ctl[0]: task cursor, ctl[1]: error flag, ctl[2..]: per-segment counters
+    __shared__ c32 lds[kLdsElems];
+    __shared__ uint32_t s_task, s_ok;
+    for (;;) {
+        // lane index made opaque per task: keeps the compiler from lifting
+        // every routine's lane-derived addresses out of the loop (they
+        // would all stay live across tasks)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (tid == 0)
+            s_task = atomicAdd(&ctl[0], 1u);
+        __syncthreads();
+        const uint32_t ti = s_task;
+        __syncthreads();
+        if (ti >= n_tasks)
+            break;
+        const Task t = tasks[ti];
+        const Tables tb = tables[t.kind];
+        switch (t.kind) {
+        case K256: run_single<Sh256, P256, D>(lds, tb, t, items, in, out, tid); break;
+        case K1000: run_single<Sh1000, P1000, D>(lds, tb, t, items, in, out, tid); break;
+        case K1024: run_single<Sh1024, P1024, D>(lds, tb, t, items, in, out, tid); break;
+        case K1536: run_single<Sh1536, P1536, D>(lds, tb, t, items, in, out, tid); break;
+        case K4096: run_single<Sh4096, P4096, D>(lds, tb, t, items, in, out, tid); break;
+        case K6000: run_single<Sh6000, P6000, D>(lds, tb, t, items, in, out, tid); break;
+        case K16384A: {
+            const Item it = items[t.item];
+            column_tile<Sh128, PCol128, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, in + it.in_off,
+                                           ybuf + it.y_off, (int)t.tile * PCol128::C, 128);
+            signal_done(&ctl[2 + t.dep], tid);
+            break;
+        }
+        case K65536A: {
+            const Item it = items[t.item];
+            column_tile<Sh256c, PCol256, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid,
+                                            in + it.in_off, ybuf + it.y_off,
+                                            (int)t.tile * PCol256::C, 256);
+            signal_done(&ctl[2 + t.dep], tid);
+            break;
+        }
+        case K16384B: {
+            const Item it = items[t.item];
+            if (wait_for(&ctl[2 + t.dep], 128 / PCol128::C, &ctl[1], tid, &s_ok))
+                row_tile<Sh128, PRow128, D>(lds, tb.tw, tid, ybuf + it.y_off,
+                                            out + it.out_off, (int)t.tile * PRow128::C, 128);
+            break;
+        }
+        case K65536B: {
+            const Item it = items[t.item];
+            if (wait_for(&ctl[2 + t.dep], 256 / PCol256::C, &ctl[1], tid, &s_ok))
+                row_tile<Sh256c, PRow256, D>(lds, tb.tw, tid, ybuf + it.y_off,
+                                             out + it.out_off, (int)t.tile * PRow256::C, 256);
+            break;
+        }
+        case K1MA: {
+            const Item it = items[t.item];
+            column_tile<Sh1k, PCol1k, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, in + it.in_off,
+                                         ybuf + it.y_off, (int)t.tile * PCol1k::C, 1024);
+            signal_done(&ctl[2 + t.dep], tid);
+            break;
+        }
+        case K1MB: {
+            const Item it = items[t.item];
+            if (wait_for(&ctl[2 + t.dep], 1024 / PCol1k::C, &ctl[1], tid, &s_ok))
+                row_tile<Sh1k, PRow1k, D>(lds, tb.tw, tid, ybuf + it.y_off, out + it.out_off,
+                                          (int)t.tile * PRow1k::C, 1024);
+            break;
+        }
+        default: break;
+        }
+        __syncthreads();  // LDS and s_task reuse by the next task
+    }
+}
+
+// zero the cursor, the error flag and the counters (a kernel rather than a
+// memset so the whole launch sequence can be captured into a graph)
+__global__ void __launch_bounds__(256) clear_kernel(uint32_t *ctl, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        ctl[i] = 0u;
+}
+
+struct LengthInfo {
+    uint32_t n;
+    bool two_pass;
+    Kind a, b;       // single pass: a only
+    int per_task;    // single pass: segments per tile; two pass: tiles per pass
+    int n1, n2;
+};
+
+const LengthInfo kLengths[] = {
+    {256, false, K256, K256, P256::S, 0, 0},
+    {1000, false, K1000, K1000, P1000::S, 0, 0},
+    {1024, false, K1024, K1024, P1024::S, 0, 0},
+    {1536, false, K1536, K1536, P1536::S, 0, 0},
+    {4096, false, K4096, K4096, P4096::S, 0, 0},
+    {6000, false, K6000, K6000, P6000::S, 0, 0},
+    {16384, true, K16384A, K16384B, 128 / PCol128::C, 128, 128},
+    {65536, true, K65536A, K65536B, 256 / PCol256::C, 256, 256},
+    {1u << 20, true, K1MA, K1MB, 1024 / PCol1k::C, 1024, 1024},
+};
+
+const LengthInfo *length_info(uint32_t n)
+{
+    for (const LengthInfo &l : kLengths)
+        if (l.n == n)
+            return &l;
+    return nullptr;
+}
+
+}  // namespace wl
+
+struct WorkList {
+    int dir = -1;
+    int device = 0;
+    // per-kind twiddle tables, built once
+    wl::Tables *d_tables = nullptr;
+    std::vector<void *> table_mem;
+    // the current entries
+    uint64_t n_items = 0;
+    uint64_t max_in = 0, max_out = 0;  // highest sample touched (+1)
+    bool in_place_ok = false;          // outputs hit no other entry's input
+    uint32_t n_tasks = 0, n_dep = 0;
+    uint64_t counts[wl::KCOUNT] = {};
+    uint64_t samples = 0;
+    size_t y_bytes = 0;
+    unsigned grid = 1;
+    // device arrays, grown on demand
+    wl::Task *d_tasks = nullptr;
+    size_t cap_tasks = 0;
+    wl::Item *d_items = nullptr;
+    size_t cap_items = 0;
+    uint32_t *d_ctl = nullptr;
+    size_t cap_ctl = 0;
+    c32 *d_y = nullptr;
+    size_t cap_y = 0;
+    // pinned staging of the task/item upload
+    void *h_stage = nullptr;
+    size_t cap_stage = 0;
+    hipEvent_t stage_done = nullptr;
+    // graph replay
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_in = nullptr;
+    void *graph_out = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    void drop_graph()
+    {
+        if (graph_exec)
+            (void)hipGraphExecDestroy(graph_exec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
+
+    ~WorkList()
+    {
+        drop_graph();
+        if (capture_stream)
+            (void)hipStreamDestroy(capture_stream);
+        if (stage_done)
+            (void)hipEventDestroy(stage_done);
+        if (h_stage)
+            (void)hipHostFree(h_stage);
+        for (void *p : {(void *)d_tasks, (void *)d_items, (void *)d_tables, (void *)d_ctl,
+                        (void *)d_y})
+            if (p)
+                (void)hipFree(p);
+        for (void *p : table_mem)
+            if (p)
+                (void)hipFree(p);
+    }
+};
+
+namespace {
+
+std::vector<c32> roots(uint64_t n)
+{
+    std::vector<c32> t(n);
+    for (uint64_t m = 0; m < n; ++m)
+        t[m] = root_forward(m, n);
+    return t;
+}
+
+int wl_tables(WorkList *w)
+{
+    using namespace wl;
+    std::vector<Tables> tables(KCOUNT, Tables{nullptr, nullptr, nullptr, 0, 0});
+    auto up = [&](const std::vector<c32> &v, const c32 **out) -> int {
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, v.size() * sizeof(c32));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FFT_ERR_OUT_OF_MEMORY, "twiddle table");
+        }
+        w->table_mem.push_back(d);
+        if ((e = hipMemcpy(d, v.data(), v.size() * sizeof(c32), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return hip_error(e, "twiddle upload");
+        *out = (const c32 *)d;
+        return FFT_OK;
+    };
+    int st;
+    for (const LengthInfo &L : kLengths) {
+        if (!L.two_pass) {
+            if ((st = up(roots(L.n), &tables[L.a].tw)) != FFT_OK)
+                return st;
+            continue;
+        }
+        if ((st = up(roots((uint64_t)L.n1), &tables[L.a].tw)) != FFT_OK ||
+            (st = up(roots((uint64_t)L.n2), &tables[L.b].tw)) != FFT_OK)
+            return st;
+        int sh = 0;
+        while ((1ull << sh) * (1ull << sh) < L.n)
+            ++sh;
+        const uint64_t lo = 1ull << sh;
+        std::vector<c32> tl(lo), th((L.n + lo - 1) / lo);
+        for (uint64_t j = 0; j < lo; ++j)
+            tl[j] = root_forward(j, L.n);
+        for (uint64_t j = 0; j < th.size(); ++j)
+            th[j] = root_forward(j * lo, L.n);
+        if ((st = up(tl, &tables[L.a].tl)) != FFT_OK || (st = up(th, &tables[L.a].th)) != FFT_OK)
+            return st;
+        tables[L.a].sh = sh;
+    }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, tables.size() * sizeof(Tables));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "table index");
+    }
+    w->d_tables = (Tables *)d;
+    if ((e = hipMemcpy(d, tables.data(), tables.size() * sizeof(Tables),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_error(e, "table index upload");
+    return FFT_OK;
+}
+
+// host-side checks and task compilation; fills the WorkList's metadata
+int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::Task> &tasks,
+               std::vector<wl::Item> &hitems)
+{
+    using namespace wl;
+    constexpr size_t NL = sizeof(kLengths) / sizeof(kLengths[0]);
+    std::vector<std::vector<uint32_t>> bucket(NL);
+    uint64_t max_in = 0, max_out = 0, samples = 0;
+    if (n > 0xffffffffull)
+        return set_error(FFT_ERR_INVALID_ARG, "work list too long");
+    for (size_t i = 0; i < n; ++i) {
+        const LengthInfo *li = length_info(items[i].segment_len);
+        if (!li)
+            return set_error(FFT_ERR_UNSUPPORTED_LENGTH,
+                             "work item %zu: length %u has no work-list routine", i,
+                             items[i].segment_len);
+        const uint64_t len = items[i].segment_len;
+        if (items[i].in_off > (UINT64_MAX >> 4) - len || items[i].out_off > (UINT64_MAX >> 4) - len)
+            return set_error(FFT_ERR_INVALID_ARG, "work item %zu: offset out of range", i);
+        max_in = std::max<uint64_t>(max_in, items[i].in_off + len);
+        max_out = std::max<uint64_t>(max_out, items[i].out_off + len);
+        bucket[li - kLengths].push_back((uint32_t)i);
+        samples += len;
+    }
+    // outputs must not overlap each other
+    {
+        std::vector<std::pair<uint64_t, uint64_t>> r(n);
+        for (size_t i = 0; i < n; ++i)
+            r[i] = {items[i].out_off, items[i].out_off + items[i].segment_len};
+        std::sort(r.begin(), r.end());
+        for (size_t i = 1; i < n; ++i)
+            if (r[i].first < r[i - 1].second)
+                return set_error(FFT_ERR_OVERLAP, "two work items write overlapping outputs");
+    }
+    // with in_base == out_base an output may only coincide with its own
+    // input: inputs sorted by start, prefix top-2 of their ends; an output
+    // [a, b) meets input j iff start_j < b and end_j > a
+    bool in_place_ok = true;
+    if (n) {
+        std::vector<size_t> ord(n);
+        for (size_t i = 0; i < n; ++i)
+            ord[i] = i;
+        std::sort(ord.begin(), ord.end(),
+                  [&](size_t x, size_t y) { return items[x].in_off < items[y].in_off; });
+        std::vector<uint64_t> starts(n);
+        for (size_t k = 0; k < n; ++k)
+            starts[k] = items[ord[k]].in_off;
+        std::vector<std::pair<uint64_t, size_t>> best(n), second(n);
+        std::pair<uint64_t, size_t> b1{0, SIZE_MAX}, b2{0, SIZE_MAX};
+        for (size_t k = 0; k < n; ++k) {
+            const size_t j = ord[k];
+            const std::pair<uint64_t, size_t> e{items[j].in_off + items[j].segment_len, j};
+            if (e.first > b1.first) {
+                b2 = b1;
+                b1 = e;
+            } else if (e.first > b2.first) {
+                b2 = e;
+            }
+            best[k] = b1;
+            second[k] = b2;
+        }
+        for (size_t i = 0; i < n && in_place_ok; ++i) {
+            const uint64_t a = items[i].out_off, b = a + items[i].segment_len;
+            const size_t k =
+                (size_t)(std::lower_bound(starts.begin(), starts.end(), b) - starts.begin());
+            if (k == 0)
+                continue;
+            const auto &m1 = best[k - 1], &m2 = second[k - 1];
+            const bool own_same = items[i].in_off == a;
+            if (m1.first > a && !(m1.second == i && own_same))
+                in_place_ok = false;
+            else if (m1.second == i && own_same && m2.first > a)
+                in_place_ok = false;
+        }
+    }
+    // tasks: all pass-A tiles, then single-pass tiles, then pass-B tiles;
+    // longest lengths first within each group
+    tasks.clear();
+    hitems.clear();
+    hitems.reserve(n);
+    std::vector<Task> a_tasks, s_tasks, b_tasks;
+    uint64_t y_samples = 0;
+    uint32_t dep = 0;
+    uint64_t counts[KCOUNT] = {};
+    for (int li = (int)NL - 1; li >= 0; --li) {
+        const LengthInfo &L = kLengths[li];
+        const auto &b = bucket[li];
+        if (L.two_pass) {
+            for (uint32_t idx : b) {
+                const uint32_t item = (uint32_t)hitems.size();
+                hitems.push_back({items[idx].in_off, items[idx].out_off, y_samples});
+                y_samples += L.n;
+                for (int t = 0; t < L.per_task; ++t) {
+                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, dep, {0, 0, 0}});
+                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, dep, {0, 0, 0}});
+                }
+                counts[L.a] += 1;
+                ++dep;
+            }
+        } else {
+            for (size_t k = 0; k < b.size(); k += (size_t)L.per_task) {
+                const uint32_t first = (uint32_t)hitems.size();
+                const uint32_t cnt = (uint32_t)std::min<size_t>(L.per_task, b.size() - k);
+                for (uint32_t j = 0; j < cnt; ++j)
+                    hitems.push_back({items[b[k + j]].in_off, items[b[k + j]].out_off, 0});
+                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, {0, 0, 0}});
+                counts[L.a] += cnt;
+            }
+        }
+    }
+    tasks.reserve(a_tasks.size() + s_tasks.size() + b_tasks.size());
+    tasks.insert(tasks.end(), a_tasks.begin(), a_tasks.end());
+    tasks.insert(tasks.end(), s_tasks.begin(), s_tasks.end());
+    tasks.insert(tasks.end(), b_tasks.begin(), b_tasks.end());
+    if (tasks.size() > 0xffffffffull)
+        return set_error(FFT_ERR_INVALID_ARG, "work list too long");
+    w->n_items = n;
+    w->max_in = max_in;
+    w->max_out = max_out;
+    w->samples = samples;
+    w->in_place_ok = in_place_ok;
+    w->n_tasks = (uint32_t)tasks.size();
+    w->n_dep = dep;
+    w->y_bytes = y_samples * sizeof(c32);
+    std::memcpy(w->counts, counts, sizeof(counts));
+    return FFT_OK;
+}
+
+template <class T>
+int grow(T **ptr, size_t *cap, size_t need, const char *what)
+{
+    if (need <= *cap)
+        return FFT_OK;
+    const size_t want = std::max(need, *cap * 2);
+    if (*ptr)
+        (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    void *d = nullptr;
+    if (hipMalloc(&d, want * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "%s (%zu bytes)", what, want * sizeof(T));
+    }
+    *ptr = (T *)d;
+    *cap = want;
+    return FFT_OK;
+}
+
+// compile and upload new entries; device arrays grow (after a device-wide
+// synchronisation) when they are too small; the upload goes through
+// pinned staging on `stream`, ordered before later work on that stream
+int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
+{
+    using namespace wl;
+    std::vector<Task> tasks;
+    std::vector<Item> hitems;
+    int st = wl_compile(w, items, n, tasks, hitems);
+    if (st != FFT_OK)
+        return st;
+    const size_t need_ctl = 2 + (size_t)w->n_dep;
+    const size_t need_y = w->y_bytes / sizeof(c32);
+    if (tasks.size() > w->cap_tasks || hitems.size() > w->cap_items || need_ctl > w->cap_ctl ||
+        need_y > w->cap_y) {
+        (void)hipDeviceSynchronize();  // old arrays may still be in use
+        w->drop_graph();
+        if ((st = grow(&w->d_tasks, &w->cap_tasks, std::max<size_t>(tasks.size(), 1), "tasks")) !=
+                FFT_OK ||
+            (st = grow(&w->d_items, &w->cap_items, std::max<size_t>(hitems.size(), 1), "items")) !=
+                FFT_OK ||
+            (st = grow(&w->d_ctl, &w->cap_ctl, need_ctl, "counters")) != FFT_OK ||
+            (st = grow(&w->d_y, &w->cap_y, std::max<size_t>(need_y, 1), "two-pass scratch")) !=
+                FFT_OK)
+            return st;
+    }
+    const size_t tb = tasks.size() * sizeof(Task), ib = hitems.size() * sizeof(Item);
+    hipError_t e;
+    if (!w->stage_done && (e = hipEventCreateWithFlags(&w->stage_done, hipEventDisableTiming)) !=
+                              hipSuccess)
+        return hip_error(e, "hipEventCreate");
+    // the previous upload must have left the staging buffer
+    if ((e = hipEventSynchronize(w->stage_done)) != hipSuccess)
+        return hip_error(e, "hipEventSynchronize");
+    if (tb + ib > w->cap_stage) {
+        if (w->h_stage)
+            (void)hipHostFree(w->h_stage);
+        w->h_stage = nullptr;
+        w->cap_stage = 0;
+        const size_t want = std::max(tb + ib, w->cap_stage * 2);
+        if (hipHostMalloc(&w->h_stage, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            w->h_stage = nullptr;
+            return set_error(FFT_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes", want);
+        }
+        w->cap_stage = want;
+    }
+    std::memcpy(w->h_stage, tasks.data(), tb);
+    std::memcpy((char *)w->h_stage + tb, hitems.data(), ib);
+    if (tb && (e = hipMemcpyAsync(w->d_tasks, w->h_stage, tb, hipMemcpyHostToDevice, s)) !=
+                  hipSuccess)
+        return hip_error(e, "task upload");
+    if (ib && (e = hipMemcpyAsync(w->d_items, (char *)w->h_stage + tb, ib,
+                                  hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_error(e, "item upload");
+    if ((e = hipEventRecord(w->stage_done, s)) != hipSuccess)
+        return hip_error(e, "hipEventRecord");
+    const void *k = w->dir < 0 ? (const void *)&worklist_kernel<-1> : (const void *)&worklist_kernel<1>;
+    const unsigned g = grid_for(k, kThreads, std::max<uint64_t>(1, w->n_tasks), w->device, 1);
+    if (g != w->grid)
+        w->drop_graph();  // the captured launch has the old grid
+    w->grid = g;
+    return set_ok();
+}
+
+int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
+{
+    using namespace wl;
+    if (w->n_tasks == 0)
+        return set_ok();
+    const uint32_t nctl = 2 + w->n_dep;
+    hipLaunchKernelGGL(clear_kernel, dim3(std::min<uint32_t>((nctl + 255) / 256, 1024)),
+                       dim3(256), 0, s, w->d_ctl, nctl);
+    if (w->dir < 0)
+        hipLaunchKernelGGL((worklist_kernel<-1>), dim3(w->grid), dim3(kThreads), 0, s,
+                           w->d_tasks, w->n_tasks, w->d_items, w->d_tables, (const c32 *)in,
+                           (c32 *)out, w->d_y, w->d_ctl);
+    else
+        hipLaunchKernelGGL((worklist_kernel<1>), dim3(w->grid), dim3(kThreads), 0, s,
+                           w->d_tasks, w->n_tasks, w->d_items, w->d_tables, (const c32 *)in,
+                           (c32 *)out, w->d_y, w->d_ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_error(e, "work-list launch");
+    return set_ok();
+}
+
+int wl_check_io(WorkList *w, const void *in, void *out)
+{
+    if (!in || !out)
+        return set_error(FFT_ERR_INVALID_ARG, "in_base/out_base must not be NULL");
+    if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
+        return set_error(FFT_ERR_ALIGNMENT, "bases must be 8-byte aligned");
+    if (w->n_tasks == 0)
+        return FFT_OK;
+    if (in == out && !w->in_place_ok)
+        return set_error(FFT_ERR_OVERLAP,
+                         "in_base == out_base but an output range overlaps another entry's input");
+    if (in != out) {
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        const uint64_t ai = w->max_in * sizeof(c32), bo = w->max_out * sizeof(c32);
+        if (a < b + bo && b < a + ai)
+            return set_error(FFT_ERR_OVERLAP, "in and out buffers overlap without being equal");
+    }
+    int st = check_device_range(in, w->max_in * sizeof(c32), "in_base");
+    if (st != FFT_OK)
+        return st;
+    if (out != in && (st = check_device_range(out, w->max_out * sizeof(c32), "out_base")) != FFT_OK)
+        return st;
+    return FFT_OK;
+}
+
+}  // namespace
+}  // namespace fftseg
+
+using namespace fftseg;
+
+extern "C" fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direction)
+{
+    try {
+        if (!items && n) {
+            set_error(FFT_ERR_INVALID_ARG, "items is NULL");
+            return nullptr;
+        }
+        if (direction != FFT_FORWARD && direction != FFT_INVERSE) {
+            set_error(FFT_ERR_INVALID_ARG, "direction must be -1 or +1");
+            return nullptr;
+        }
+        WorkList *w = new WorkList();
+        w->dir = direction;
+        // host-side checks first: nothing touches the device for bad entries
+        std::vector<wl::Task> tasks;
+        std::vector<wl::Item> hitems;
+        int st = wl_compile(w, items, n, tasks, hitems);
+        if (st == FFT_OK && hipGetDevice(&w->device) != hipSuccess) {
+            (void)hipGetLastError();
+            st = set_error(FFT_ERR_HIP, "no HIP device available");
+        }
+        if (st == FFT_OK)
+            st = wl_tables(w);
+        if (st == FFT_OK)
+            st = wl_reset(w, items, n, nullptr);
+        if (st == FFT_OK && hipStreamSynchronize(nullptr) != hipSuccess)
+            st = hip_error(hipGetLastError(), "hipStreamSynchronize");
+        if (st != FFT_OK) {
+            const int code = last_status();
+            std::string msg = last_message();
+            delete w;
+            set_error(code, "%s", msg.c_str());
+            return nullptr;
+        }
+        return reinterpret_cast<fft_worklist_t>(w);
+    } catch (...) {
+        set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+        return nullptr;
+    }
+}
+
+extern "C" int fft_worklist_reset(fft_worklist_t wlh, const fft_work_t *items, size_t n,
+                                  void *stream)
+{
+    try {
+        WorkList *w = reinterpret_cast<WorkList *>(wlh);
+        if (!w)
+            return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
+        if (!items && n)
+            return set_error(FFT_ERR_INVALID_ARG, "items is NULL");
+        return wl_reset(w, items, n, (hipStream_t)stream);
+    } catch (...) {
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+extern "C" int fft_exec_worklist(fft_worklist_t wlh, const void *in_base, void *out_base,
+                                 void *stream)
+{
+    WorkList *w = reinterpret_cast<WorkList *>(wlh);
+    if (!w)
+        return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
+    int st = wl_check_io(w, in_base, out_base);
+    if (st != FFT_OK)
+        return st;
+    return wl_enqueue(w, in_base, out_base, (hipStream_t)stream);
+}
+
+extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, void *out_base,
+                                       void *stream)
+{
+    WorkList *w = reinterpret_cast<WorkList *>(wlh);
+    if (!w)
+        return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
+    int st = wl_check_io(w, in_base, out_base);
+    if (st != FFT_OK)
+        return st;
+    if (w->n_tasks == 0)
+        return set_ok();
+    hipError_t e;
+    if (!w->graph_exec || w->graph_in != in_base || w->graph_out != out_base) {
+        w->drop_graph();
+        if (!w->capture_stream &&
+            (e = hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_error(e, "hipStreamCreate");
+        if ((e = hipStreamBeginCapture(w->capture_stream, hipStreamCaptureModeThreadLocal)) !=
+            hipSuccess)
+            return hip_error(e, "hipStreamBeginCapture");
+        st = wl_enqueue(w, in_base, out_base, w->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(w->capture_stream, &g);
+        if (st != FFT_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return hip_error(e, "hipStreamEndCapture");
+        w->graph = g;
+        if ((e = hipGraphInstantiate(&w->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            w->graph_exec = nullptr;
+            return hip_error(e, "hipGraphInstantiate");
+        }
+        w->graph_in = in_base;
+        w->graph_out = out_base;
+    }
+    if ((e = hipGraphLaunch(w->graph_exec, (hipStream_t)stream)) != hipSuccess)
+        return hip_error(e, "hipGraphLaunch");
+    return set_ok();
+}
+
+extern "C" int fft_worklist_status(fft_worklist_t wlh, void *stream)
+{
+    WorkList *w = reinterpret_cast<WorkList *>(wlh);
+    if (!w)
+        return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_error(e, "hipStreamSynchronize");
+    if (!w->d_ctl || w->n_tasks == 0)
+        return set_ok();
+    uint32_t flag = 0;
+    if ((e = hipMemcpy(&flag, w->d_ctl + 1, sizeof(flag), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_error(e, "status read");
+    if (flag)
+        return set_error(FFT_ERR_TIMEOUT, "a two-pass tile gave up waiting for its first pass");
+    return set_ok();
+}
+
+extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
+{
+    const WorkList *w = reinterpret_cast<const WorkList *>(wlh);
+    if (!w)
+        return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
+    std::string js = "{\"items\":" + std::to_string(w->n_items) +
+                     ",\"tasks\":" + std::to_string(w->n_tasks) +
+                     ",\"two_pass_segments\":" + std::to_string(w->n_dep) +
+                     ",\"samples\":" + std::to_string(w->samples) +
+                     ",\"scratch_bytes\":" + std::to_string(w->y_bytes) +
+                     ",\"in_place_ok\":" + (w->in_place_ok ? "true" : "false") +
+                     ",\"grid\":" + std::to_string(w->grid) + ",\"segments_per_length\":{";
+    bool first = true;
+    for (const wl::LengthInfo &L : wl::kLengths) {
+        if (!w->counts[L.a])
+            continue;
+        js += std::string(first ? "" : ",") + "\"" + std::to_string(L.n) +
+              "\":" + std::to_string(w->counts[L.a]);
+        first = false;
+    }
+    js += "}}";
+    if (buf && len) {
+        const size_t k = std::min(len - 1, js.size());
+        std::memcpy(buf, js.data(), k);
+        buf[k] = 0;
+    }
+    set_ok();
+    return (int)js.size();
+}
+
+extern "C" int fft_worklist_destroy(fft_worklist_t wlh)
+{
+    WorkList *w = reinterpret_cast<WorkList *>(wlh);
+    if (w) {
+        (void)hipDeviceSynchronize();
+        delete w;
+    }
+    return set_ok();
+}
+
+extern "C" int fft_worklist_supported(uint32_t segment_len)
+{
+    set_ok();
+    return wl::length_info(segment_len) != nullptr;
+}

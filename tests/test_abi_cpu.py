@@ -74,3 +74,17 @@ def test_factorize_matches_lengths():
 def test_variants_compiled_for_workload_lengths():
     for n in (256, 1000, 1024, 1536, 4096, 6000, 16384):
         assert fs.variant_count(n) >= 2, n
+
+
+def test_split_info_and_forced_variants_are_checked():
+    assert fs.split_info(4096) is None            # single pass
+    assert fs.split_info(3 ** 9) is None          # radix-stage fallback
+    n1, n2, nc, nr = fs.split_info(1 << 20)
+    assert n1 * n2 == 1 << 20 and nc >= 2 and nr >= 2
+    with pytest.raises(fs.FFTError) as e:
+        fs.Plan(4096, 4, split_variants=(0, 0))
+    assert e.value.name == "FFT_ERR_INVALID_ARG"
+    with pytest.raises(fs.FFTError):
+        fs.Plan(1 << 20, 4, split_variants=(nc, 0))
+    with pytest.raises(fs.FFTError):
+        fs.Plan(4096, 4, variant=fs.variant_count(4096) + 3)

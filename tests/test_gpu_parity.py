@@ -70,6 +70,25 @@ def test_every_variant(n):
             check(n, run(n, x, d, variant=v), x, d, what="variant %d dir %d" % (v, d))
 
 
+@pytest.mark.parametrize("n", [1 << 15, 1 << 16, 1 << 18, 1 << 20, 1 << 22])
+def test_every_four_step_tile_variant(n):
+    n1, n2, nc, nr = fs.split_info(n)
+    assert n1 * n2 == n and nc >= 1 and nr >= 1
+    b = 3 if n < 1 << 20 else 2
+    x = noise(n, b, seed=n + 17)
+    ref = {d: oracle.fft_recursive(x, n, d) for d in (fs.FORWARD, fs.INVERSE)}
+    for c in range(nc):
+        for r in range(nr):
+            announce("n=%d split %dx%d column variant %d row variant %d" % (n, n1, n2, c, r))
+            for d in (fs.FORWARD, fs.INVERSE):
+                import torch
+                xd = torch.from_numpy(x.reshape(-1)).cuda()
+                with fs.Plan(n, b, d, split_variants=(c, r)) as p:
+                    y = p.exec(xd).cpu().numpy().reshape(b, n)
+                e = oracle.rel_l2(y, ref[d])
+                assert np.all(e <= oracle.tolerance(n)), (c, r, d, e.max())
+
+
 @pytest.mark.parametrize("n", [1024, 4096, 6000, 1 << 16, 3 ** 9, 5])
 def test_in_place_equals_out_of_place_and_deterministic(n):
     b = ragged_batch(n)

@@ -1,0 +1,113 @@
+"""Streaming through pinned host slots (fill -> H2D -> transform -> D2H ->
+drain): every chunk against the oracle, callback failures, caller-owned
+pinned buffers."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1407_6915_amd as fs
+import siggen
+
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def host_view(ptr, nbytes):
+    buf = (ctypes.c_char * nbytes).from_address(ptr)
+    return np.frombuffer(buf, dtype=np.complex64)
+
+
+def run_stream(n, batch, n_chunks, sig, n_slots=3, fail_fill=None, fail_drain=None,
+               native_fill=False):
+    got = {}
+
+    def fill(c, ptr, nbytes):
+        if c == fail_fill:
+            return 5
+        sig.fill_ptr(c * batch * n, batch * n, ptr)
+        return 0
+
+    def drain(c, ptr, nbytes):
+        if c == fail_drain:
+            return 9
+        got[c] = host_view(ptr, nbytes).copy().reshape(batch, n)
+        return 0
+
+    plan = fs.Plan(n, batch)
+    if native_fill:
+        src = sig.chunk_source(0, batch * n)
+        rc, failed, st = plan.exec_stream(n_chunks, src, drain, n_slots)
+    else:
+        rc, failed, st = plan.exec_stream(n_chunks, fill, drain, n_slots)
+    plan.close()
+    return rc, failed, st, got
+
+
+@pytest.mark.parametrize("n,batch,n_chunks,n_slots", [(4096, 64, 7, 3), (1000, 50, 4, 2),
+                                                      (1 << 16, 3, 5, 3)])
+def test_stream_every_chunk(n, batch, n_chunks, n_slots):
+    announce("stream n=%d batch=%d chunks=%d slots=%d" % (n, batch, n_chunks, n_slots))
+    sig = siggen.Signal(seed=99, seg_len=n, sigma=1.0, tones=[(7, 0.5, 0.0)])
+    rc, failed, st, got = run_stream(n, batch, n_chunks, sig, n_slots)
+    assert rc == 0 and failed is None
+    assert st["chunks_done"] == n_chunks and sorted(got) == list(range(n_chunks))
+    assert st["bytes_h2d"] == n_chunks * batch * n * 8
+    for c in range(n_chunks):
+        x = sig.segments(c * batch, batch)
+        err = oracle.rel_l2(got[c], oracle.fft_recursive(x, n))
+        assert np.all(err <= oracle.tolerance(n)), (c, err.max())
+
+
+def test_stream_native_fill_and_chirp():
+    n, batch, chunks = 1 << 20, 2, 3
+    announce("stream 2^20 native fill")
+    sig = siggen.Signal(seed=5, seg_len=n, sigma=0.0, chirp_amp=1.0)
+    rc, failed, st, got = run_stream(n, batch, chunks, sig, 3, native_fill=True)
+    assert rc == 0 and st["chunks_done"] == chunks
+    t = np.arange(n, dtype=np.int64)
+    want = np.sqrt(n) * np.exp(1j * np.pi / 4) * np.exp(-1j * np.pi * ((t * t) % (2 * n)) / n)
+    for c in range(chunks):
+        for s in range(batch):
+            assert oracle.rel_l2(got[c][s][None], want[None])[0] <= oracle.tolerance(n)
+
+
+@pytest.mark.parametrize("where", ["fill", "drain"])
+def test_stream_callback_failure_reports_chunk(where):
+    n, batch, chunks = 1024, 16, 8
+    announce("stream failure in %s" % where)
+    sig = siggen.Signal(seed=1, seg_len=n, sigma=1.0)
+    kw = {"fail_fill": 5} if where == "fill" else {"fail_drain": 3}
+    rc, failed, st, got = run_stream(n, batch, chunks, sig, 3, **kw)
+    assert rc == -7  # FFT_ERR_CALLBACK
+    bad = 5 if where == "fill" else 3
+    assert failed == bad
+    # every chunk below the failing one was handed out, correct
+    assert sorted(got) == list(range(bad))
+    for c in range(bad):
+        x = sig.segments(c * batch, batch)
+        assert np.all(oracle.rel_l2(got[c], oracle.fft_recursive(x, n)) <= oracle.tolerance(n))
+    # the pipeline is reusable after a failure: resume from the failed chunk
+    rc2, failed2, st2, got2 = run_stream(n, batch, 2, sig, 3)
+    assert rc2 == 0 and failed2 is None
+
+
+def test_stream_pinned_buffers():
+    import torch
+    n, batch, chunks = 4096, 32, 6
+    announce("stream pinned")
+    sig = siggen.Signal(seed=3, seg_len=n, sigma=1.0)
+    ins = [torch.from_numpy(sig.segments(c * batch, batch).reshape(-1)).pin_memory()
+           for c in range(chunks)]
+    outs = [torch.empty(batch * n, dtype=torch.complex64).pin_memory() for _ in range(chunks)]
+    plan = fs.Plan(n, batch)
+    st = plan.exec_stream_pinned(chunks, [t.data_ptr() for t in ins],
+                                 [t.data_ptr() for t in outs], 3)
+    plan.close()
+    assert st["chunks_done"] == chunks
+    for c in range(chunks):
+        x = ins[c].numpy().reshape(batch, n)
+        y = outs[c].numpy().reshape(batch, n)
+        assert np.all(oracle.rel_l2(y, oracle.fft_recursive(x, n)) <= oracle.tolerance(n))

@@ -1,0 +1,172 @@
+"""The persistent work-list kernel on uneven batches: every segment against
+the oracle, in place, graph replay, agreement with plain per-length plans,
+and the full 200000-segment uneven workload on sampled segments."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1407_6915_amd as fs
+import siggen
+from siggen import workloads
+
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [256, 1000, 1024, 1536, 4096, 6000, 16384, 65536]
+
+
+def packed(lengths, gap=0, seed=0):
+    """Back-to-back layout in list order (optionally with gaps); returns
+    in offsets, out offsets (a different permutation of slots) and total."""
+    offs = np.zeros(len(lengths), np.int64)
+    pos = 0
+    for i, n in enumerate(lengths):
+        offs[i] = pos
+        pos += n + gap
+    return offs, pos
+
+
+def to_entries(in_off, out_off, lengths):
+    arr = np.zeros(len(lengths), dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                                        ("segment_len", "<u4"), ("job", "<u4")])
+    arr["in_off"], arr["out_off"], arr["segment_len"] = in_off, out_off, lengths
+    arr["job"] = np.arange(len(lengths))
+    return arr
+
+
+def check_all(x_host, y_host, in_off, out_off, lengths, direction=fs.FORWARD, sample=None):
+    idx = range(len(lengths)) if sample is None else sample
+    worst = 0.0
+    for i in idx:
+        n = int(lengths[i])
+        x = x_host[in_off[i]:in_off[i] + n]
+        ref = oracle.fft_recursive(x, n, direction)
+        e = oracle.rel_l2(y_host[out_off[i]:out_off[i] + n][None], ref)[0]
+        assert e <= oracle.tolerance(n), (i, n, e)
+        worst = max(worst, e / oracle.tolerance(n))
+    print("  worst error / bound = %.3f" % worst, flush=True)
+
+
+@pytest.mark.parametrize("direction", [fs.FORWARD, fs.INVERSE])
+def test_mixed_lengths_every_segment(direction):
+    import torch
+    rng = np.random.default_rng(7)
+    lengths = np.array(rng.choice(LENGTHS, 60).tolist() + LENGTHS, np.int64)
+    rng.shuffle(lengths)
+    announce("work list %d segments dir=%d" % (len(lengths), direction))
+    in_off, total = packed(lengths, gap=3)
+    # outputs in reverse order, in a buffer of their own
+    out_off, out_total = packed(lengths[::-1])
+    out_off = out_off[::-1].copy()
+    x = siggen.Signal(seed=11, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(out_total, dtype=torch.complex64, device="cuda")
+    with fs.WorkList(to_entries(in_off, out_off, lengths), direction) as wl:
+        d = wl.describe()
+        assert d["items"] == len(lengths)
+        wl.exec(xd, yd)
+        wl.status()
+        y = yd.cpu().numpy()
+        check_all(x, y, in_off, out_off, lengths, direction)
+        # graph replay equals the eager launch, several replays with eager
+        # work in between
+        for _ in range(3):
+            yd.zero_()
+            wl.exec(xd, yd, graph=True)
+            wl.status()
+            assert np.array_equal(yd.cpu().numpy(), y)
+            xd.add_(0)
+    # agreement with plain per-length plans on the same segments
+    for n in LENGTHS:
+        sel = np.nonzero(lengths == n)[0]
+        seg = np.stack([x[in_off[i]:in_off[i] + n] for i in sel])
+        xs = torch.from_numpy(seg.reshape(-1)).cuda()
+        with fs.Plan(n, len(sel), direction) as p:
+            ys = p.exec(xs).cpu().numpy().reshape(len(sel), n)
+        mine = np.stack([y[out_off[i]:out_off[i] + n] for i in sel])
+        e = oracle.rel_l2(mine, ys.astype(np.complex128))
+        assert np.all(e <= 2 * oracle.tolerance(n)), (n, e.max())
+
+
+def test_in_place_and_overlap_rules():
+    import torch
+    lengths = np.array([4096, 65536, 256, 16384, 1000, 6000, 1536, 1024] * 3, np.int64)
+    announce("work list in place")
+    off, total = packed(lengths)
+    x = siggen.Signal(seed=12, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    with fs.WorkList(to_entries(off, off, lengths)) as wl:
+        wl.exec(xd, xd)
+        wl.status()
+    check_all(x, xd.cpu().numpy(), off, off, lengths)
+    # two entries that swap places cannot run in place (each output lands
+    # on the other's input), but can run out of place
+    ent = to_entries(np.array([0, 4096]), np.array([4096, 0]), np.array([4096, 4096]))
+    x2 = siggen.Signal(seed=13, seg_len=1, sigma=1.0).samples(0, 8192)
+    xd2 = torch.from_numpy(x2).cuda()
+    with fs.WorkList(ent) as wl:
+        with pytest.raises(fs.FFTError) as e:
+            wl.exec(xd2, xd2)
+        assert e.value.name == "FFT_ERR_OVERLAP"
+        yd2 = torch.zeros_like(xd2)
+        wl.exec(xd2, yd2)
+        wl.status()
+    check_all(x2, yd2.cpu().numpy(), [0, 4096], [4096, 0], [4096, 4096])
+
+
+def test_bounds_are_checked():
+    """A work list reaching past the end of its buffer's allocation is
+    refused.  The case runs only after the HIP runtime itself reports the
+    raw allocation's exact extent, which is what the library's check reads,
+    so no kernel can start on it."""
+    import ctypes
+    import torch
+    announce("work list bounds")
+    hip = ctypes.CDLL("libamdhip64.so")
+    torch.cuda.synchronize()
+    p = ctypes.c_void_p()
+    nbytes = 1 << 20
+    assert hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(nbytes)) == 0
+    try:
+        base, size = ctypes.c_void_p(), ctypes.c_size_t()
+        rc = hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), p)
+        if rc == 0 and base.value == p.value and size.value == nbytes:
+            n_fit = nbytes // 8
+            with fs.WorkList([(0, 0, 4096), (n_fit, n_fit, 4096)]) as wl:
+                with pytest.raises(fs.FFTError) as e:
+                    wl.exec_ptr(p.value, p.value, 0)
+                assert e.value.name == "FFT_ERR_BOUNDS"
+    finally:
+        hip.hipFree(p)
+
+
+def test_uneven_workload_full_size():
+    import torch
+    lengths = workloads.uneven_lengths()
+    n_seg = len(lengths)
+    in_off = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+    total = int(lengths.sum())
+    announce("uneven workload: %d segments, %d samples" % (n_seg, total))
+    sig = workloads.uneven_signal()
+    xd = torch.empty(total, dtype=torch.complex64, device="cuda")
+    chunk = 1 << 27
+    for a in range(0, total, chunk):
+        m = min(chunk, total - a)
+        xd[a:a + m].copy_(torch.from_numpy(sig.samples(a, m)))
+    yd = torch.empty_like(xd)
+    with fs.WorkList(to_entries(in_off, in_off, lengths)) as wl:
+        wl.exec(xd, yd)
+        wl.status()
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for n in workloads.UNEVEN_LENGTHS:
+        sel = rng.choice(np.nonzero(lengths == n)[0], 16, replace=False)
+        for i in sel:
+            a = int(in_off[i])
+            x = sig.samples(a, n)
+            y = yd[a:a + n].cpu().numpy()
+            e = oracle.rel_l2(y[None], oracle.fft_recursive(x, n))[0]
+            assert e <= oracle.tolerance(n), (n, i, e)
+            worst = max(worst, e / oracle.tolerance(n))
+    print("  sampled 16 per length, worst error / bound %.3f" % worst, flush=True)
