@@ -27,7 +27,7 @@ def _short(name: str) -> str:
     name = name.strip('"')
     if name.startswith("void "):
         name = name[5:]
-    return name if len(name) < 160 else name[:157] + "..."
+    return name if len(name) < 400 else name[:397] + "..."
 
 
 def kernels(stats_csv: str, out_md: str, command: str) -> None:

@@ -125,7 +125,7 @@ def streamed(args):
     sig = workloads.long_signal()
     plan = fs.Plan(n, seg)
     # host-link reference: plain pinned copies of one chunk each way
-    hb = torch.empty(chunk_samples, dtype=torch.complex64).pin_memory()
+    hb = torch.empty(chunk_samples, dtype=torch.complex64, pin_memory=True)
     db = torch.empty(chunk_samples, dtype=torch.complex64, device="cuda")
     t_h2d = _time(torch, lambda: db.copy_(hb, non_blocking=True), 3, 1)
     t_d2h = _time(torch, lambda: hb.copy_(db, non_blocking=True), 3, 1)
@@ -133,8 +133,10 @@ def streamed(args):
     # (1) pre-generated pinned pool, cycled: the host link and the pipeline
     pool = 4
     t0 = time.perf_counter()
-    ins = [torch.empty(chunk_samples, dtype=torch.complex64).pin_memory() for _ in range(pool)]
-    outs = [torch.empty(chunk_samples, dtype=torch.complex64).pin_memory() for _ in range(pool)]
+    ins = [torch.empty(chunk_samples, dtype=torch.complex64, pin_memory=True)
+           for _ in range(pool)]
+    outs = [torch.empty(chunk_samples, dtype=torch.complex64, pin_memory=True)
+            for _ in range(pool)]
     for c in range(pool):
         sig.fill_ptr(c * chunk_samples, chunk_samples, ins[c].data_ptr())
     t_pool = time.perf_counter() - t0
@@ -190,8 +192,8 @@ def serving(args):
     rng = np.random.default_rng(5)
     pool_samples = 1 << 32                                 # 32 GiB pinned payload pool
     t0 = time.perf_counter()
-    pool = torch.empty(pool_samples, dtype=torch.complex64).pin_memory()
-    outp = torch.empty(pool_samples, dtype=torch.complex64).pin_memory()
+    pool = torch.empty(pool_samples, dtype=torch.complex64, pin_memory=True)
+    outp = torch.empty(pool_samples, dtype=torch.complex64, pin_memory=True)
     gen = workloads.job_signal(workloads.Job(0, 0.0, 4096, 1))
     chunk = 1 << 28
     for a in range(0, pool_samples, chunk):
@@ -215,10 +217,14 @@ def serving(args):
     max_launch = 1 << 31                                   # bounds the two-pass scratch
     arena_samples = (budget_bytes - max_launch * 8) // 8
     ex = GpuExecutor(arena_samples)
-    # saturation of the plain path: every job queued at t = 0
-    sat_jobs = job_states(1e9, min(args.jobs, 300), 99)
-    st_sat = serve_fifo(sat_jobs, plans, fifo_arena)
+    # saturation: the same jobs, every one queued at t = 0, through each path
+    sat_f = job_states(1e9, min(args.jobs, 300), 99)
+    sat_c = [JobState(j.index, j.arrival_s, j.seg_len, j.n_seg, j.host_in, j.host_out)
+             for j in sat_f]
+    st_sat = serve_fifo(sat_f, plans, fifo_arena)
     lam_sat = st_sat["jobs_per_s"]
+    ex.t0 = time.perf_counter()
+    st_sat_c = serve(sat_c, ex, arena_samples, max_launch_samples=max_launch)
     rows = []
     for k, frac in enumerate(float(r) for r in args.rates.split(",")):
         lam = frac * lam_sat
@@ -241,6 +247,10 @@ def serving(args):
         p.close()
     print(json.dumps({"workload": "serving", "jobs_per_rate": args.jobs,
                       "plain_saturation_jobs_per_s": round(lam_sat, 2),
+                      "continuous_saturation_jobs_per_s": round(st_sat_c["jobs_per_s"], 2),
+                      "saturation_payload_GBps": {
+                          "plain": round(st_sat["samples_per_s"] * 8 / 1e9, 2),
+                          "continuous": round(st_sat_c["samples_per_s"] * 8 / 1e9, 2)},
                       "hbm_budget_bytes": budget_bytes, "pool_fill_s": round(t_pool, 2),
                       "rates": rows}), flush=True)
     return 0

@@ -6,14 +6,22 @@
 namespace fftseg {
 namespace {
 
-// flag bits: streamed global access, twiddles reloaded per tile,
-// XCD-aware tile order
-constexpr int kNT = 1, kNoHoist = 2, kXcd = 4;
+// flag bits: streamed global access; twiddles reloaded per tile (all
+// stages, or all but the last); XCD-aware tile order; register allocation
+// for 2 waves per SIMD
+constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16;
+
+template <int NS, int F>
+constexpr int hoist_mask()
+{
+    return (F & kNoHoist) ? 0 : (F & kHoistLast) ? (1 << (NS - 1)) : -1;
+}
 
 template <int M, int T, int C, int PS, int F, int... Rs>
 struct ColInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
-    using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, (F & kNoHoist) == 0, (F & kXcd) != 0>;
+    using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                             (F & kXcd) != 0, (F & kW2) ? 2 : 1>;
     static void launch(int dir, const void *in, void *ybuf, const void *tw,
                        const void *tl, const void *th, int sh, int n2,
                        uint64_t batch, unsigned grid, hipStream_t s)
@@ -51,7 +59,8 @@ struct ColInst {
 template <int M, int T, int C, int PS, int F, int... Rs>
 struct RowInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
-    using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, (F & kNoHoist) == 0, (F & kXcd) != 0>;
+    using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                          (F & kXcd) != 0, (F & kW2) ? 2 : 1>;
     static void launch(int dir, const void *ybuf, void *out, const void *tw, int n1,
                        uint64_t batch, unsigned grid, hipStream_t s)
     {
@@ -92,6 +101,7 @@ const ColumnDesc kColumns[] = {
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
     ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
     ColInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
@@ -99,6 +109,8 @@ const ColumnDesc kColumns[] = {
     ColInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
     ColInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
+    ColInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
+    ColInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
 };
@@ -110,6 +122,7 @@ const RowDesc kRows[] = {
     RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
+    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
     RowInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
     RowInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
@@ -117,6 +130,8 @@ const RowDesc kRows[] = {
     RowInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
     RowInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
+    RowInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
+    RowInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),
     RowInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
 };

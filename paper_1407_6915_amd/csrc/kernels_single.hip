@@ -9,14 +9,29 @@
 namespace fftseg {
 namespace {
 
-// F: flag bits, kNT = streamed (non-temporal) global access, kNoHoist =
-// twiddle loads stay inside the persistent loop.
-constexpr int kNT = 1, kNoHoist = 2;
+// F: flag bits.  kNT = streamed (non-temporal) global access; kNoHoist =
+// every stage reloads its twiddles per segment; kHoistLast = only the last
+// stage keeps its twiddles in registers across segments (default: all
+// stages do); kW2 / kW3 = the register allocation must allow 2 / 3 waves
+// per SIMD.
+constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16;
+
+template <int NS, int F>
+constexpr int hoist_mask()
+{
+    return (F & kNoHoist) ? 0 : (F & kHoistLast) ? (1 << (NS - 1)) : -1;
+}
+template <int F>
+constexpr int waves()
+{
+    return (F & kW3) ? 3 : (F & kW2) ? 2 : 1;
+}
 
 template <int N, int T, int S, int PS, int F, int... Rs>
 struct SpInst {
     using Sh = Shape<N, T, Radices<Rs...>>;
-    using Pol = SinglePassPolicy<Sh, S, PS, (F & kNT) != 0, (F & kNoHoist) == 0>;
+    using Pol = SinglePassPolicy<Sh, S, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                                 false, waves<F>()>;
 
     static void launch(int dir, const void *in, void *out, const void *tw,
                        uint64_t batch, unsigned grid, hipStream_t s)
@@ -39,7 +54,7 @@ struct SpInst {
         d.segs_per_wg = S;
         d.pad_shift = PS;
         d.nontemporal = (F & kNT) != 0;
-        d.hoist = (F & kNoHoist) == 0;
+        d.hoist = hoist_mask<sizeof...(Rs), F>();
         d.lds_bytes = Pol::kLdsElems * (int)sizeof(c32);
         d.nrad = (int)sizeof...(Rs);
         const int r[] = {Rs...};
@@ -77,19 +92,22 @@ const SinglePassDesc kTable[] = {
     SpInst<2048, 128, 2, 4, kNT, 16, 16, 8>::desc(0, 16),
     SpInst<2048, 128, 1, 4, kNT, 16, 16, 8>::desc(1, 16),
     SpInst<2048, 64, 2, 4, kNT, 16, 16, 8>::desc(2, 16),
-    SpInst<4096, 128, 2, 4, kNT, 16, 16, 16>::desc(0, 32),
-    SpInst<4096, 128, 2, 4, 0, 16, 16, 16>::desc(1, 32),
-    SpInst<4096, 128, 2, 0, kNT, 16, 16, 16>::desc(2, 32),
-    SpInst<4096, 256, 1, 4, kNT, 16, 16, 16>::desc(3, 32),
-    SpInst<4096, 256, 1, 0, kNT, 16, 16, 16>::desc(4, 32),
-    SpInst<4096, 512, 1, 4, kNT, 8, 8, 8, 8>::desc(5, 32),
-    SpInst<4096, 128, 2, 4, kNT, 16, 16, 16>::desc(6, 64),
+    SpInst<4096, 128, 2, 4, kNT | kHoistLast | kW2, 16, 16, 16>::desc(0, 32),
+    SpInst<4096, 128, 2, 4, kNT | kNoHoist | kW2, 16, 16, 16>::desc(1, 32),
+    SpInst<4096, 128, 2, 4, kNT | kW2, 16, 16, 16>::desc(2, 32),
+    SpInst<4096, 128, 2, 4, kNT, 16, 16, 16>::desc(3, 32),
+    SpInst<4096, 256, 1, 4, kNT, 16, 16, 16>::desc(4, 32),
+    SpInst<4096, 256, 1, 0, kNT, 16, 16, 16>::desc(5, 32),
+    SpInst<4096, 512, 1, 4, kNT, 8, 8, 8, 8>::desc(6, 32),
+    SpInst<4096, 256, 1, 4, kNT | kHoistLast | kW3, 16, 16, 16>::desc(7, 32),
     SpInst<8192, 512, 1, 4, kNT, 16, 16, 16, 2>::desc(0, 4),
     SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(1, 4),
     SpInst<8192, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 2>::desc(2, 4),
+    SpInst<8192, 512, 1, 4, kNT | kHoistLast | kW2, 16, 16, 16, 2>::desc(3, 8),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(0, 8),
     SpInst<16384, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(1, 8),
     SpInst<16384, 1024, 1, 4, kNoHoist, 16, 16, 16, 4>::desc(2, 8),
+    SpInst<16384, 1024, 1, 0, kNT | kNoHoist, 16, 16, 16, 4>::desc(3, 8),
     // mixed radix 2/3/5
     SpInst<1000, 100, 2, 4, kNT, 10, 10, 10>::desc(0, 32),
     SpInst<1000, 100, 2, 4, 0, 10, 10, 10>::desc(1, 32),
@@ -102,6 +120,7 @@ const SinglePassDesc kTable[] = {
     SpInst<6000, 400, 1, 4, 0, 16, 15, 25>::desc(1, 16),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(2, 0),
     SpInst<6000, 300, 1, 4, kNT | kNoHoist, 20, 20, 15>::desc(3, 0),
+    SpInst<6000, 400, 1, 4, kNT | kHoistLast | kW2, 16, 15, 25>::desc(4, 16),
 };
 
 }  // namespace

@@ -24,7 +24,7 @@ struct SinglePassDesc {
     int segs_per_wg;    // segments per workgroup (S)
     int pad_shift;      // one LDS pad element every 2^pad_shift (0: none)
     int nontemporal;    // streamed (non-temporal) global loads and stores
-    int hoist;          // twiddles may stay in registers across segments
+    int hoist;          // bit i: stage i keeps its twiddles in registers across segments
     int grid_mult;      // default persistent grid: resident waves of workgroups
     int lds_bytes;
     int nrad;

@@ -154,12 +154,75 @@ __device__ __forceinline__ void st_scatter(const c32 *v, int t, Put &&put)
     }
 }
 
+// LDS exchange.  Pol::lds(c, i) is the padded LDS slot of element i of tile
+// column c; when a stride of `step` elements keeps its padding pattern
+// (step a multiple of the padding period, or one run of R unit steps
+// starting on a period boundary) the R accesses of a butterfly are one base
+// address plus compile-time offsets, so no per-element address registers
+// are needed.
+template <class Pol, int STEP, int R>
+struct LdsRun {
+    static constexpr bool kStrided = Pol::template strided<STEP>();
+    static constexpr bool kUnitRun = (STEP == 1) && Pol::template unit_run<R>();
+    static constexpr bool kSep = kStrided || kUnitRun;
+    static constexpr int kStride = kStrided ? Pol::template stride<STEP>() : Pol::template stride<1>();
+};
+
+template <class St, class Sh, class Pol, int L>
+__device__ __forceinline__ void lds_scatter(const c32 *v, int t, int c, c32 *lds)
+{
+    using Run = LdsRun<Pol, L, St::R>;
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            const int base = (b / L) * (L * St::R) + (b % L);
+            if constexpr (Run::kSep) {
+                c32 *p = lds + Pol::lds(c, base);
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    p[r * Run::kStride] = v[u * St::R + r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    lds[Pol::lds(c, base + r * L)] = v[u * St::R + r];
+            }
+        }
+    }
+}
+
+template <class St, class Sh, class Pol>
+__device__ __forceinline__ void lds_gather(c32 *v, int t, int c, const c32 *lds)
+{
+    using Run = LdsRun<Pol, St::NB, St::R>;
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            if constexpr (Run::kStrided) {
+                const c32 *p = lds + Pol::lds(c, b);
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    v[u * St::R + r] = p[r * Run::kStride];
+            } else {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    v[u * St::R + r] = lds[Pol::lds(c, b + r * St::NB)];
+            }
+        }
+    }
+}
+
 // Run stages I.. of a tile.  Pol supplies the lane mapping per stage
 // (col<I>, thr<I>), the LDS address of element i of tile column c, and the
 // final store (which sees the last stage's outputs at b + r*NB).
+// `tid` drives addressing and `tid_tw` the twiddle indices: the caller may
+// make `tid` opaque per loop iteration so lane-derived addresses are
+// recomputed (cheap) instead of held in registers across a persistent
+// loop, while twiddles indexed by `tid_tw` can still stay in registers.
 template <class Sh, class Pol, int D, int I, int L>
 __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
-                                         const c32 *__restrict__ tw, int tid,
+                                         const c32 *__restrict__ tw, int tid, int tid_tw,
                                          const typename Pol::Ctx &ctx)
 {
     using St = Stage<Sh, I, L>;
@@ -167,22 +230,30 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
     const int t = Pol::template thr<I>(tid);
     const bool act = Pol::active(tid);
     if (act)
-        st_compute<St, Sh, L, D, Pol::kHoist>(v, t, tw);
+        st_compute<St, Sh, L, D, Pol::hoists(I)>(v, Pol::template thr<I>(tid_tw), tw);
     if constexpr (St::kLast) {
         if (act)
             Pol::template store<St, D>(v, t, c, ctx);
     } else {
         if (act)
-            st_scatter<St, Sh, L>(v, t, [&](int i, c32 a) { lds[Pol::lds(c, i)] = a; });
+            lds_scatter<St, Sh, Pol, L>(v, t, c, lds);
         __syncthreads();
         using Nx = Stage<Sh, I + 1, L * St::R>;
         const int c2 = Pol::template col<I + 1>(tid);
         const int t2 = Pol::template thr<I + 1>(tid);
         if (act)
-            st_gather<Nx, Sh>(v, t2, [&](int i) { return lds[Pol::lds(c2, i)]; });
+            lds_gather<Nx, Sh, Pol>(v, t2, c2, lds);
         __syncthreads();
-        tile_run<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, ctx);
+        tile_run<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, tid_tw, ctx);
     }
+}
+
+// a copy of the lane index the compiler cannot treat as loop-invariant
+__device__ __forceinline__ int opaque_lane()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,15 +261,19 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
 //   lane mapping: segment slot = tid / T, thread t = tid % T (all stages);
 //   LDS: slot * SegStride + i + (i >> PS) (one pad element every 2^PS).
 // (Partial = the workgroup may have more threads than S*T; the extra
-// threads only take part in barriers.)
-template <class Sh, int S_, int PS_, bool NT_ = false, bool Hoist_ = true,
-          bool Partial_ = false>
+// threads only take part in barriers.  HoistMask bit i lets stage i keep its
+// twiddles in registers across the segments of a persistent loop.  Waves =
+// the waves per SIMD the register allocation must allow.)
+template <class Sh, int S_, int PS_, bool NT_ = false, int HoistMask_ = -1,
+          bool Partial_ = false, int Waves_ = 1>
 struct SinglePassPolicy {
     static constexpr int S = S_;
     static constexpr int PS = PS_;
     static constexpr bool kNT = NT_;
-    static constexpr bool kHoist = Hoist_;
+    static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kPartial = Partial_;
+    static constexpr int kWaves = Waves_;
+    static constexpr bool hoists(int stage) { return (kHoistMask >> stage) & 1; }
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kSegStride = pad(Sh::M - 1) + 1;
     static constexpr int kLdsElems = Sh::NS > 1 ? S * kSegStride : 1;
@@ -217,6 +292,13 @@ struct SinglePassPolicy {
     {
         return !kPartial || tid < kThreads;
     }
+    // padding-aware strides (see LdsRun)
+    template <int STEP>
+    static constexpr bool strided() { return PS <= 0 || STEP % (1 << PS) == 0; }
+    template <int STEP>
+    static constexpr int stride() { return PS > 0 ? STEP + (STEP >> PS) : STEP; }
+    template <int R>
+    static constexpr bool unit_run() { return PS > 0 && R == (1 << PS); }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int, const Ctx &ctx)
@@ -239,7 +321,7 @@ struct SinglePassPolicy {
 // writes y_c (valid_c false for an empty slot).
 template <class Sh, class Pol, int D>
 __device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
-                                            const c32 *x, c32 *y, bool valid)
+                                            int tid_tw, const c32 *x, c32 *y, bool valid)
 {
     const int t = Pol::template thr<0>(tid);
     typename Pol::Ctx ctx{y, valid && Pol::active(tid)};
@@ -247,21 +329,21 @@ __device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw
     using S0 = Stage<Sh, 0, 1>;
     if (ctx.valid)
         st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 template <class Sh, class Pol, int D>
-__global__ void __launch_bounds__(Pol::kThreads)
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     single_pass_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
                        uint64_t batch)
 {
     __shared__ c32 lds[Pol::kLdsElems];
-    const int tid = threadIdx.x;
-    const int slot = Pol::template col<0>(tid);
+    const int tid_tw = threadIdx.x;
     const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
     for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const uint64_t seg = g * Pol::S + slot;
-        single_tile<Sh, Pol, D>(lds, tw, tid, in + seg * Sh::M, out + seg * Sh::M,
+        const int tid = opaque_lane();
+        const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+        single_tile<Sh, Pol, D>(lds, tw, tid, tid_tw, in + seg * Sh::M, out + seg * Sh::M,
                                 seg < batch);
     }
 }
@@ -306,14 +388,16 @@ struct FourStepCtx {
 };
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
-template <class Sh, int C_, int PS_, bool NT_ = false, bool Hoist_ = true,
-          bool Xcd_ = false>
+template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
+          bool Xcd_ = false, int Waves_ = 1>
 struct ColumnPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
     static constexpr bool kNT = NT_;
-    static constexpr bool kHoist = Hoist_;
+    static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kXcd = Xcd_;
+    static constexpr int kWaves = Waves_;
+    static constexpr bool hoists(int stage) { return (kHoistMask >> stage) & 1; }
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kLdsElems = (pad(Sh::M - 1) + 1) * C;
     static constexpr int kThreads = Sh::T * C;
@@ -324,6 +408,12 @@ struct ColumnPolicy {
     static __device__ __forceinline__ int thr(int tid) { return tid / C; }
     static __device__ __forceinline__ int lds(int c, int i) { return pad(i) * C + c; }
     static __device__ __forceinline__ bool active(int) { return true; }
+    template <int STEP>
+    static constexpr bool strided() { return PS <= 0 || STEP % (1 << PS) == 0; }
+    template <int STEP>
+    static constexpr int stride() { return (PS > 0 ? STEP + (STEP >> PS) : STEP) * C; }
+    template <int R>
+    static constexpr bool unit_run() { return PS > 0 && R == (1 << PS); }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
@@ -355,7 +445,7 @@ template <class Sh, class Pol, int D>
 __device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw,
                                             const c32 *__restrict__ tl,
                                             const c32 *__restrict__ th, int sh, int tid,
-                                            const c32 *x, c32 *y, int first, int n2)
+                                            int tid_tw, const c32 *x, c32 *y, int first, int n2)
 {
     FourStepCtx ctx{x, y, first, Sh::M, n2, tl, th, sh, true};
     const int c = Pol::template col<0>(tid);
@@ -364,11 +454,11 @@ __device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw
     using S0 = Stage<Sh, 0, 1>;
     const c32 *xc = x + first + c;
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 template <class Sh, class Pol, int D>
-__global__ void __launch_bounds__(Pol::kThreads)
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     four_step_columns_kernel(const c32 *in, c32 *ybuf, const c32 *__restrict__ tw,
                              const c32 *__restrict__ tl, const c32 *__restrict__ th,
                              int sh, int n2, uint64_t batch)
@@ -383,22 +473,24 @@ __global__ void __launch_bounds__(Pol::kThreads)
             continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh, threadIdx.x, in + seg * nseg,
-                                ybuf + seg * nseg, first, n2);
+        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh, opaque_lane(), threadIdx.x,
+                                in + seg * nseg, ybuf + seg * nseg, first, n2);
     }
 }
 
 // Pass B: lanes row-major (c = tid / T, t = tid % T) up to the last stage,
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
-template <class Sh, int C_, int PS_, bool NT_ = false, bool Hoist_ = true,
-          bool Xcd_ = false>
+template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
+          bool Xcd_ = false, int Waves_ = 1>
 struct RowPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
     static constexpr bool kNT = NT_;
-    static constexpr bool kHoist = Hoist_;
+    static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kXcd = Xcd_;
+    static constexpr int kWaves = Waves_;
+    static constexpr bool hoists(int stage) { return (kHoistMask >> stage) & 1; }
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kRow = (pad(Sh::M - 1) + 1) | 1;  // odd row stride
     static constexpr int kLdsElems = kRow * C;
@@ -416,6 +508,12 @@ struct RowPolicy {
     }
     static __device__ __forceinline__ int lds(int c, int i) { return c * kRow + pad(i); }
     static __device__ __forceinline__ bool active(int) { return true; }
+    template <int STEP>
+    static constexpr bool strided() { return PS <= 0 || STEP % (1 << PS) == 0; }
+    template <int STEP>
+    static constexpr int stride() { return PS > 0 ? STEP + (STEP >> PS) : STEP; }
+    template <int R>
+    static constexpr bool unit_run() { return PS > 0 && R == (1 << PS); }
 
     template <class St, int D>
     static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
@@ -439,7 +537,7 @@ struct RowPolicy {
 // segment, x: segment output, n1 rows).
 template <class Sh, class Pol, int D>
 __device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
-                                         const c32 *y, c32 *x, int first, int n1)
+                                         int tid_tw, const c32 *y, c32 *x, int first, int n1)
 {
     static_assert(Sh::NS > 1, "the row pass changes lane mapping through LDS");
     FourStepCtx ctx{y, x, first, n1, Sh::M, nullptr, nullptr, 0, true};
@@ -449,11 +547,11 @@ __device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, i
     using S0 = Stage<Sh, 0, 1>;
     const c32 *yr = y + (size_t)(first + c) * Sh::M;
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 template <class Sh, class Pol, int D>
-__global__ void __launch_bounds__(Pol::kThreads)
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     four_step_rows_kernel(const c32 *ybuf, c32 *out, const c32 *__restrict__ tw,
                           int n1, uint64_t batch)
 {
@@ -467,8 +565,8 @@ __global__ void __launch_bounds__(Pol::kThreads)
             continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        row_tile<Sh, Pol, D>(lds, tw, threadIdx.x, ybuf + seg * nseg, out + seg * nseg,
-                             first, n1);
+        row_tile<Sh, Pol, D>(lds, tw, opaque_lane(), threadIdx.x, ybuf + seg * nseg,
+                             out + seg * nseg, first, n1);
     }
 }
 

@@ -7,8 +7,9 @@
 //   single pass  up to S whole segments of one length (S = 16 for 256, ...)
 //   two pass     one column tile (pass A) or row tile (pass B) of a
 //                four-step segment (16384 = 128 x 128, 65536 = 256 x 256)
-// Workgroups claim tasks through an atomic cursor in list order: all pass-A
-// tiles first, then single-pass tasks (longest first), then pass-B tiles.
+// Workgroups claim tasks (a few at a time) through an atomic cursor in list
+// order: all pass-A tasks first, then single-pass tasks (longest first),
+// then pass-B tasks.
 // A pass-B tile waits until its segment's pass-A tiles have signalled a
 // per-segment counter.  Those tiles were claimed earlier by workgroups that
 // are running and never wait, so every wait ends; a bounded spin still
@@ -49,11 +50,13 @@ struct Item {          // one segment
 
 struct Task {
     uint32_t kind;
-    uint32_t item;   // first item of the task (items sorted per task)
-    uint32_t count;  // single pass: segments in the tile
-    uint32_t tile;   // two pass: column/row block; counter index in dep
-    uint32_t dep;    // two pass: per-segment counter index
-    uint32_t pad[3];
+    uint32_t item;    // single pass: first item; two pass: the segment's item
+    uint32_t count;   // single pass: segments in the task (whole tiles of S)
+    uint32_t tile;    // two pass: first column/row block
+    uint32_t ntiles;  // two pass: blocks in the task
+    uint32_t dep;     // two pass: per-segment counter index
+    uint32_t need;    // pass B: first-pass tasks of the segment to wait for
+    uint32_t pad;
 };
 
 struct Tables {      // per kind, device pointers
@@ -65,28 +68,28 @@ struct Tables {      // per kind, device pointers
 
 constexpr int kThreads = 256;
 
-// routine shapes
+// routine shapes (streamed global access, twiddles reloaded per task)
 using Sh256 = Shape<256, 16, Radices<16, 16>>;
-using P256 = SinglePassPolicy<Sh256, 16, 4, false, false, false>;
+using P256 = SinglePassPolicy<Sh256, 16, 4, true, 0, false>;
 using Sh1000 = Shape<1000, 100, Radices<10, 10, 10>>;
-using P1000 = SinglePassPolicy<Sh1000, 2, 4, false, false, true>;
+using P1000 = SinglePassPolicy<Sh1000, 2, 4, true, 0, true>;
 using Sh1024 = Shape<1024, 64, Radices<16, 16, 4>>;
-using P1024 = SinglePassPolicy<Sh1024, 4, 4, false, false, false>;
+using P1024 = SinglePassPolicy<Sh1024, 4, 4, true, 0, false>;
 using Sh1536 = Shape<1536, 96, Radices<16, 16, 6>>;
-using P1536 = SinglePassPolicy<Sh1536, 2, 4, false, false, true>;
+using P1536 = SinglePassPolicy<Sh1536, 2, 4, true, 0, true>;
 using Sh4096 = Shape<4096, 256, Radices<16, 16, 16>>;
-using P4096 = SinglePassPolicy<Sh4096, 1, 4, false, false, false>;
+using P4096 = SinglePassPolicy<Sh4096, 1, 4, true, 0, false>;
 using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
-using P6000 = SinglePassPolicy<Sh6000, 1, 4, false, false, false>;
+using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false>;
 using Sh128 = Shape<128, 8, Radices<16, 8>>;
-using PCol128 = ColumnPolicy<Sh128, 32, 4, false, false>;
-using PRow128 = RowPolicy<Sh128, 32, 4, false, false>;
+using PCol128 = ColumnPolicy<Sh128, 32, 4, true, 0>;
+using PRow128 = RowPolicy<Sh128, 32, 4, true, 0>;
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
-using PCol256 = ColumnPolicy<Sh256c, 16, 4, false, false>;
-using PRow256 = RowPolicy<Sh256c, 16, 4, false, false>;
+using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0>;
+using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0>;
 using Sh1k = Shape<1024, 64, Radices<16, 16, 4>>;
-using PCol1k = ColumnPolicy<Sh1k, 4, 4, false, false>;
-using PRow1k = RowPolicy<Sh1k, 4, 4, false, false>;
+using PCol1k = ColumnPolicy<Sh1k, 4, 4, true, 0>;
+using PRow1k = RowPolicy<Sh1k, 4, 4, true, 0>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLdsElems =
@@ -108,15 +111,57 @@ static_assert(PCol128::kThreads == kThreads && PRow128::kThreads == kThreads &&
 // spin bound for a pass-B wait (~tens of ms, far above one tile's time)
 constexpr uint32_t kSpinLimit = 1u << 20;
 
+// tasks claimed per atomic on the cursor
+constexpr uint32_t kClaim = 4;
+
+// a value the compiler must recompute per loop iteration (see below)
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Every loop below passes an opaque copy of the lane index down: the
+// routines of all kinds are inlined into one kernel, and lane-derived
+// addresses lifted out of the loops would all stay live at once.
 template <class Sh, class Pol, int D>
 __device__ __forceinline__ void run_single(c32 *lds, const Tables &tb, const Task &t,
                                            const Item *__restrict__ items, const c32 *in,
-                                           c32 *out, int tid)
+                                           c32 *out, int tid0)
 {
-    const int slot = tid / Sh::T;
-    const bool valid = Pol::active(tid) && slot < (int)t.count;
-    const Item it = valid ? items[t.item + slot] : Item{0, 0, 0};
-    single_tile<Sh, Pol, D>(lds, tb.tw, tid, in + it.in_off, out + it.out_off, valid);
+    for (uint32_t first = 0; first < t.count; first += Pol::S) {
+        const int tid = opaque(tid0);
+        const int slot = tid / Sh::T;
+        const bool valid = Pol::active(tid) && first + slot < t.count;
+        const Item it = valid ? items[t.item + first + slot] : Item{0, 0, 0};
+        single_tile<Sh, Pol, D>(lds, tb.tw, tid, tid, in + it.in_off, out + it.out_off, valid);
+    }
+}
+
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void run_columns(c32 *lds, const Tables &tb, const Task &t,
+                                            const Item *__restrict__ items, const c32 *in,
+                                            c32 *ybuf, int tid0, int n2)
+{
+    const Item it = items[t.item];
+    for (uint32_t k = 0; k < t.ntiles; ++k) {
+        const int tid = opaque(tid0);
+        column_tile<Sh, Pol, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, tid, in + it.in_off,
+                                ybuf + it.y_off, (int)(t.tile + k) * Pol::C, n2);
+    }
+}
+
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void run_rows(c32 *lds, const Tables &tb, const Task &t,
+                                         const Item *__restrict__ items, const c32 *ybuf,
+                                         c32 *out, int tid0, int n1)
+{
+    const Item it = items[t.item];
+    for (uint32_t k = 0; k < t.ntiles; ++k) {
+        const int tid = opaque(tid0);
+        row_tile<Sh, Pol, D>(lds, tb.tw, tid, tid, ybuf + it.y_off, out + it.out_off,
+                             (int)(t.tile + k) * Pol::C, n1);
+    }
 }
 
 __device__ __forceinline__ void signal_done(uint32_t *counter, int tid)
@@ -166,67 +211,55 @@ __global__ void __launch_bounds__(kThreads)
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         if (tid == 0)
-            s_task = atomicAdd(&ctl[0], 1u);
+            s_task = atomicAdd(&ctl[0], kClaim);
         __syncthreads();
-        const uint32_t ti = s_task;
+        const uint32_t base = s_task;
         __syncthreads();
-        if (ti >= n_tasks)
+        if (base >= n_tasks)
             break;
-        const Task t = tasks[ti];
-        const Tables tb = tables[t.kind];
-        switch (t.kind) {
-        case K256: run_single<Sh256, P256, D>(lds, tb, t, items, in, out, tid); break;
-        case K1000: run_single<Sh1000, P1000, D>(lds, tb, t, items, in, out, tid); break;
-        case K1024: run_single<Sh1024, P1024, D>(lds, tb, t, items, in, out, tid); break;
-        case K1536: run_single<Sh1536, P1536, D>(lds, tb, t, items, in, out, tid); break;
-        case K4096: run_single<Sh4096, P4096, D>(lds, tb, t, items, in, out, tid); break;
-        case K6000: run_single<Sh6000, P6000, D>(lds, tb, t, items, in, out, tid); break;
-        case K16384A: {
-            const Item it = items[t.item];
-            column_tile<Sh128, PCol128, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, in + it.in_off,
-                                           ybuf + it.y_off, (int)t.tile * PCol128::C, 128);
-            signal_done(&ctl[2 + t.dep], tid);
-            break;
+        const uint32_t end = base + kClaim < n_tasks ? base + kClaim : n_tasks;
+        // claimed tasks run in list order: first-pass tasks precede every
+        // second-pass task in the list, so a wait below never depends on a
+        // task this workgroup still holds
+        for (uint32_t ti = base; ti < end; ++ti) {
+            tid = opaque(tid);
+            const Task t = tasks[ti];
+            const Tables tb = tables[t.kind];
+            switch (t.kind) {
+            case K256: run_single<Sh256, P256, D>(lds, tb, t, items, in, out, tid); break;
+            case K1000: run_single<Sh1000, P1000, D>(lds, tb, t, items, in, out, tid); break;
+            case K1024: run_single<Sh1024, P1024, D>(lds, tb, t, items, in, out, tid); break;
+            case K1536: run_single<Sh1536, P1536, D>(lds, tb, t, items, in, out, tid); break;
+            case K4096: run_single<Sh4096, P4096, D>(lds, tb, t, items, in, out, tid); break;
+            case K6000: run_single<Sh6000, P6000, D>(lds, tb, t, items, in, out, tid); break;
+            case K16384A:
+                run_columns<Sh128, PCol128, D>(lds, tb, t, items, in, ybuf, tid, 128);
+                signal_done(&ctl[2 + t.dep], tid);
+                break;
+            case K65536A:
+                run_columns<Sh256c, PCol256, D>(lds, tb, t, items, in, ybuf, tid, 256);
+                signal_done(&ctl[2 + t.dep], tid);
+                break;
+            case K1MA:
+                run_columns<Sh1k, PCol1k, D>(lds, tb, t, items, in, ybuf, tid, 1024);
+                signal_done(&ctl[2 + t.dep], tid);
+                break;
+            case K16384B:
+                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
+                    run_rows<Sh128, PRow128, D>(lds, tb, t, items, ybuf, out, tid, 128);
+                break;
+            case K65536B:
+                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
+                    run_rows<Sh256c, PRow256, D>(lds, tb, t, items, ybuf, out, tid, 256);
+                break;
+            case K1MB:
+                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
+                    run_rows<Sh1k, PRow1k, D>(lds, tb, t, items, ybuf, out, tid, 1024);
+                break;
+            default: break;
+            }
+            __syncthreads();  // LDS and s_task reuse by the next task
         }
-        case K65536A: {
-            const Item it = items[t.item];
-            column_tile<Sh256c, PCol256, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid,
-                                            in + it.in_off, ybuf + it.y_off,
-                                            (int)t.tile * PCol256::C, 256);
-            signal_done(&ctl[2 + t.dep], tid);
-            break;
-        }
-        case K16384B: {
-            const Item it = items[t.item];
-            if (wait_for(&ctl[2 + t.dep], 128 / PCol128::C, &ctl[1], tid, &s_ok))
-                row_tile<Sh128, PRow128, D>(lds, tb.tw, tid, ybuf + it.y_off,
-                                            out + it.out_off, (int)t.tile * PRow128::C, 128);
-            break;
-        }
-        case K65536B: {
-            const Item it = items[t.item];
-            if (wait_for(&ctl[2 + t.dep], 256 / PCol256::C, &ctl[1], tid, &s_ok))
-                row_tile<Sh256c, PRow256, D>(lds, tb.tw, tid, ybuf + it.y_off,
-                                             out + it.out_off, (int)t.tile * PRow256::C, 256);
-            break;
-        }
-        case K1MA: {
-            const Item it = items[t.item];
-            column_tile<Sh1k, PCol1k, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, in + it.in_off,
-                                         ybuf + it.y_off, (int)t.tile * PCol1k::C, 1024);
-            signal_done(&ctl[2 + t.dep], tid);
-            break;
-        }
-        case K1MB: {
-            const Item it = items[t.item];
-            if (wait_for(&ctl[2 + t.dep], 1024 / PCol1k::C, &ctl[1], tid, &s_ok))
-                row_tile<Sh1k, PRow1k, D>(lds, tb.tw, tid, ybuf + it.y_off, out + it.out_off,
-                                          (int)t.tile * PRow1k::C, 1024);
-            break;
-        }
-        default: break;
-        }
-        __syncthreads();  // LDS and s_task reuse by the next task
     }
 }
 
@@ -238,24 +271,29 @@ __global__ void __launch_bounds__(256) clear_kernel(uint32_t *ctl, uint32_t n)
         ctl[i] = 0u;
 }
 
+// Task sizes: a single-pass task is `group` whole tiles of S segments
+// (about 64 KiB of input); a two-pass segment's `tiles` column (row) blocks
+// are cut into tasks of `group` blocks.  Fewer, larger tasks keep the
+// cursor's atomics off the critical path.
 struct LengthInfo {
     uint32_t n;
     bool two_pass;
-    Kind a, b;       // single pass: a only
-    int per_task;    // single pass: segments per tile; two pass: tiles per pass
+    Kind a, b;    // single pass: a only
+    int per_tile; // single pass: segments per tile (S); two pass: blocks per pass
+    int group;    // tiles (blocks) per task
     int n1, n2;
 };
 
 const LengthInfo kLengths[] = {
-    {256, false, K256, K256, P256::S, 0, 0},
-    {1000, false, K1000, K1000, P1000::S, 0, 0},
-    {1024, false, K1024, K1024, P1024::S, 0, 0},
-    {1536, false, K1536, K1536, P1536::S, 0, 0},
-    {4096, false, K4096, K4096, P4096::S, 0, 0},
-    {6000, false, K6000, K6000, P6000::S, 0, 0},
-    {16384, true, K16384A, K16384B, 128 / PCol128::C, 128, 128},
-    {65536, true, K65536A, K65536B, 256 / PCol256::C, 256, 256},
-    {1u << 20, true, K1MA, K1MB, 1024 / PCol1k::C, 1024, 1024},
+    {256, false, K256, K256, P256::S, 2, 0, 0},
+    {1000, false, K1000, K1000, P1000::S, 4, 0, 0},
+    {1024, false, K1024, K1024, P1024::S, 2, 0, 0},
+    {1536, false, K1536, K1536, P1536::S, 3, 0, 0},
+    {4096, false, K4096, K4096, P4096::S, 2, 0, 0},
+    {6000, false, K6000, K6000, P6000::S, 2, 0, 0},
+    {16384, true, K16384A, K16384B, 128 / PCol128::C, 4, 128, 128},
+    {65536, true, K65536A, K65536B, 256 / PCol256::C, 8, 256, 256},
+    {1u << 20, true, K1MA, K1MB, 1024 / PCol1k::C, 16, 1024, 1024},
 };
 
 const LengthInfo *length_info(uint32_t n)
@@ -484,24 +522,27 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
         const LengthInfo &L = kLengths[li];
         const auto &b = bucket[li];
         if (L.two_pass) {
+            const uint32_t per_seg = (uint32_t)((L.per_tile + L.group - 1) / L.group);
             for (uint32_t idx : b) {
                 const uint32_t item = (uint32_t)hitems.size();
                 hitems.push_back({items[idx].in_off, items[idx].out_off, y_samples});
                 y_samples += L.n;
-                for (int t = 0; t < L.per_task; ++t) {
-                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, dep, {0, 0, 0}});
-                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, dep, {0, 0, 0}});
+                for (int t = 0; t < L.per_tile; t += L.group) {
+                    const uint32_t nt = (uint32_t)std::min(L.group, L.per_tile - t);
+                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, nt, dep, 0, 0});
+                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, nt, dep, per_seg, 0});
                 }
                 counts[L.a] += 1;
                 ++dep;
             }
         } else {
-            for (size_t k = 0; k < b.size(); k += (size_t)L.per_task) {
+            const size_t per_task = (size_t)L.per_tile * (size_t)L.group;
+            for (size_t k = 0; k < b.size(); k += per_task) {
                 const uint32_t first = (uint32_t)hitems.size();
-                const uint32_t cnt = (uint32_t)std::min<size_t>(L.per_task, b.size() - k);
+                const uint32_t cnt = (uint32_t)std::min<size_t>(per_task, b.size() - k);
                 for (uint32_t j = 0; j < cnt; ++j)
                     hitems.push_back({items[b[k + j]].in_off, items[b[k + j]].out_off, 0});
-                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, {0, 0, 0}});
+                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, 0, 0, 0});
                 counts[L.a] += cnt;
             }
         }

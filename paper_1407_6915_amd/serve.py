@@ -257,10 +257,11 @@ def serve(jobs: List[JobState], executor, arena_samples: int,
     n = len(jobs)
     nxt = 0
     pending: deque = deque()
-    copying: List[JobState] = []
+    # copies complete in issue order on their streams: only the head of
+    # each queue needs polling
+    copying: deque = deque()
     ready: List[JobState] = []
-    computing: List[JobState] = []
-    returning: List[JobState] = []
+    returning: deque = deque()
     finished = 0
     rejected = 0
     launch_id = 0
@@ -294,15 +295,11 @@ def serve(jobs: List[JobState], executor, arena_samples: int,
             peak_used = max(peak_used, arena.used)
             progressed = True
         # inputs that have landed
-        still = []
-        for j in copying:
-            if executor.done(j.tokens["in"]):
-                j.status = "ready"
-                ready.append(j)
-                progressed = True
-            else:
-                still.append(j)
-        copying = still
+        while copying and executor.done(copying[0].tokens["in"]):
+            j = copying.popleft()
+            j.status = "ready"
+            ready.append(j)
+            progressed = True
         # pack every ready job into one launch when the transform stream is free
         if ready and executor.stream_idle():
             batch, total = [], 0
@@ -324,17 +321,13 @@ def serve(jobs: List[JobState], executor, arena_samples: int,
             ready = rest
             progressed = True
         # spectra back on the host: release the arena
-        still = []
-        for j in returning:
-            if executor.done(j.tokens["out"]):
-                j.status = "done"
-                j.done_s = executor.now()
-                arena.release(j.off, j.samples)
-                finished += 1
-                progressed = True
-            else:
-                still.append(j)
-        returning = still
+        while returning and executor.done(returning[0].tokens["out"]):
+            j = returning.popleft()
+            j.status = "done"
+            j.done_s = executor.now()
+            arena.release(j.off, j.samples)
+            finished += 1
+            progressed = True
         if not progressed:
             until = jobs[nxt].arrival_s if nxt < n else math.inf
             executor.advance(until)
