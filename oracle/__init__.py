@@ -146,3 +146,34 @@ def record_count(file_bytes: int, n: int, bytes_per_sample: int) -> int:
 def block_count(file_bytes: int, block_bytes: int) -> int:
     """Blocks (one map task each in Sec. III) covering ``file_bytes``."""
     return -(-file_bytes // block_bytes)
+
+
+# --- overlapping, windowed segments (future work named in Sec. VI) ----------
+
+def frames(x, n: int, hop: int, n_frames: int, window=None) -> np.ndarray:
+    """The n_frames segments of a signal that start every ``hop`` samples
+    (hop < n: consecutive segments overlap), each multiplied sample by sample
+    by a real ``window`` of length n (None: rectangular), in FP64:
+
+        f_s[j] = x[s*hop + j] * w[j],   0 <= s < n_frames, 0 <= j < n.
+
+    With hop == n and no window this is the disjoint cut of Sec. III."""
+    x = np.asarray(x).reshape(-1).astype(np.complex128)
+    if hop < 1 or n_frames < 1 or (n_frames - 1) * hop + n > x.size:
+        raise ValueError("frames outside the signal")
+    out = np.empty((n_frames, n), dtype=np.complex128)
+    for s in range(n_frames):
+        out[s] = x[s * hop:s * hop + n]
+    if window is not None:
+        w = np.asarray(window, dtype=np.float64).reshape(-1)
+        if w.size != n:
+            raise ValueError("window length must equal n")
+        out *= w[None, :]
+    return out
+
+
+def short_time(x, n: int, hop: int, n_frames: int, window=None,
+               direction: int = FORWARD) -> np.ndarray:
+    """Spectra of ``frames(...)``: each frame transformed by the recursive
+    FFT of this module."""
+    return fft_recursive(frames(x, n, hop, n_frames, window), n, direction)

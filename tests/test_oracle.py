@@ -241,3 +241,55 @@ def test_paper_record_arithmetic():
     # the complex64 records used here are twice as wide
     assert oracle.record_count(g["file_bytes"], n, 8) == g["records"] // 2
     assert oracle.record_offset(5, n, 8, base=64) == 64 + 5 * 8192
+
+
+# --- overlapping, windowed segments -----------------------------------------
+
+def _hann(n):
+    # periodic Hann window 0.5 - 0.5 cos(2 pi j / n)
+    return 0.5 - 0.5 * np.cos(2 * np.pi * np.arange(n) / n)
+
+
+@pytest.mark.parametrize("n,hop,k0", [(64, 16, 5), (60, 7, 0), (32, 32, 31)])
+def test_short_time_hann_tone_closed_form(n, hop, k0):
+    """Frame s of exp(2 pi i k0 m / n) starts with phase exp(2 pi i k0 s hop / n);
+    times the periodic Hann window its spectrum is n/2 at k0 and -n/4 at
+    k0 +- 1 (mod n), all times that phase, and zero elsewhere."""
+    frames_n = 9
+    m = np.arange((frames_n - 1) * hop + n)
+    x = np.exp(2j * np.pi * k0 * m / n)
+    y = oracle.short_time(x, n, hop, frames_n, _hann(n))
+    for s in range(frames_n):
+        ph = np.exp(2j * np.pi * k0 * s * hop / n)
+        want = np.zeros(n, dtype=np.complex128)
+        want[k0] += 0.5 * n * ph
+        want[(k0 + 1) % n] += -0.25 * n * ph
+        want[(k0 - 1) % n] += -0.25 * n * ph
+        assert np.max(np.abs(y[s] - want)) < 1e-9 * n
+
+
+def test_frames_brute_force_and_disjoint_reduction():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    w = rng.uniform(0.1, 1.0, 8)
+    f = oracle.frames(x, 8, 3, 15, w)
+    for s in range(15):
+        for j in range(8):
+            assert f[s, j] == x[3 * s + j] * w[j]
+    # hop == n, no window: the disjoint records of the plain path
+    y = oracle.short_time(x[:48], 8, 8, 6)
+    assert np.array_equal(y, oracle.fft_recursive(x[:48].astype(np.complex128), 8))
+    # inverse direction is the plain inverse of each windowed frame
+    yi = oracle.short_time(x, 8, 5, 9, w, INVERSE)
+    assert np.allclose(yi, np.fft.ifft(oracle.frames(x, 8, 5, 9, w), axis=1) * 8)
+
+
+def test_frames_bad_arguments():
+    x = np.zeros(20, dtype=np.complex128)
+    with pytest.raises(ValueError):
+        oracle.frames(x, 8, 0, 2)
+    with pytest.raises(ValueError):
+        oracle.frames(x, 8, 7, 3)          # needs 2*7 + 8 = 22 samples
+    with pytest.raises(ValueError):
+        oracle.frames(x, 8, 4, 2, np.ones(7))
+    assert oracle.frames(x, 8, 6, 3).shape == (3, 8)
