@@ -177,3 +177,47 @@ def short_time(x, n: int, hop: int, n_frames: int, window=None,
     """Spectra of ``frames(...)``: each frame transformed by the recursive
     FFT of this module."""
     return fft_recursive(frames(x, n, hop, n_frames, window), n, direction)
+
+
+# --- real-input segments (Sec. III: float32 samples, 4 bytes each) ---------
+
+def real_forward(x, n: int) -> np.ndarray:
+    """Spectrum of every real length-n segment (n even), bins 0..n/2:
+
+        X_s[k] = sum_n x_s[n] exp(-2 pi i n k / N),  0 <= k <= N/2,
+
+    the remaining bins being conj(X_s[N-k]) for real input.  Computed as
+    the complex DFT of the real samples (imaginary parts zero)."""
+    a = np.asarray(x)
+    if a.dtype not in (np.float32, np.float64):
+        raise TypeError("real oracle input must be float32 or float64")
+    if n < 2 or n % 2:
+        raise ValueError("real segments need an even length")
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if a.size % n:
+        raise ValueError("input size %d is not a multiple of n=%d" % (a.size, n))
+    full = fft_recursive(a.astype(np.complex128), n, FORWARD)
+    return np.ascontiguousarray(full[:, :n // 2 + 1])
+
+
+def real_inverse(spec, n: int) -> np.ndarray:
+    """Real length-n segments from their bins 0..n/2, unnormalised:
+
+        x_s[j] = sum_{k<N} X_s[k] exp(+2 pi i j k / N),  X_s[N-k] = conj X_s[k].
+
+    Bins 0 and N/2 of a real signal are real; their imaginary parts are
+    ignored (the real part of the inverse of the Hermitian extension)."""
+    a = np.asarray(spec)
+    if a.dtype not in (np.complex64, np.complex128):
+        raise TypeError("spectrum must be complex64 or complex128")
+    if n < 2 or n % 2:
+        raise ValueError("real segments need an even length")
+    h = n // 2 + 1
+    a = np.ascontiguousarray(a, dtype=np.complex128).reshape(-1)
+    if a.size % h:
+        raise ValueError("spectrum size %d is not a multiple of n/2+1=%d" % (a.size, h))
+    a = a.reshape(-1, h)
+    full = np.empty((a.shape[0], n), dtype=np.complex128)
+    full[:, :h] = a
+    full[:, h:] = np.conj(a[:, 1:n // 2][:, ::-1])
+    return fft_recursive(full, n, INVERSE).real.copy()

@@ -293,3 +293,54 @@ def test_frames_bad_arguments():
     with pytest.raises(ValueError):
         oracle.frames(x, 8, 4, 2, np.ones(7))
     assert oracle.frames(x, 8, 6, 3).shape == (3, 8)
+
+
+# --- real-input segments -----------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 8, 1000, 1024])
+def test_real_forward_matches_numpy_rfft(n):
+    x = np.random.default_rng(n).standard_normal((5, n))
+    assert np.allclose(oracle.real_forward(x, n), np.fft.rfft(x, axis=1),
+                       rtol=1e-12, atol=1e-9 * n)
+    x32 = x.astype(np.float32)
+    assert np.allclose(oracle.real_inverse(oracle.real_forward(x32, n), n),
+                       n * x32.astype(np.float64), atol=1e-9 * n)
+
+
+@pytest.mark.parametrize("n,k0", [(64, 5), (1000, 499), (16, 8), (16, 0)])
+def test_real_cosine_closed_form(n, k0):
+    """cos(2 pi k0 j / n) has n/2 at bin k0 (n at k0 = 0 or n/2) and zeros
+    elsewhere among bins 0..n/2."""
+    j = np.arange(n)
+    y = oracle.real_forward(np.cos(2 * np.pi * k0 * j / n), n)[0]
+    want = np.zeros(n // 2 + 1)
+    want[k0] = n if k0 in (0, n // 2) else n / 2
+    assert np.max(np.abs(y - want)) < 1e-9 * n
+
+
+def test_real_inverse_definition_and_edge_bins():
+    n = 12
+    rng = np.random.default_rng(9)
+    h = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    x = oracle.real_inverse(h, n)[0]
+    # direct sum over the Hermitian extension, real bins 0 and n/2
+    full = np.concatenate([h, np.conj(h[1:6][::-1])])
+    full[0], full[6] = full[0].real, full[6].real
+    for jj in range(n):
+        s = sum(full[k] * np.exp(2j * np.pi * jj * k / n) for k in range(n))
+        assert abs(s.imag) < 1e-9 and abs(s.real - x[jj]) < 1e-9
+    # imaginary parts of bins 0 and n/2 do not matter
+    h2 = h.copy()
+    h2[0] += 3j
+    h2[6] -= 2j
+    assert np.allclose(oracle.real_inverse(h2, n), x, atol=1e-12)
+    assert np.allclose(x, np.fft.irfft(h, n) * n, atol=1e-9)
+
+
+def test_real_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.real_forward(np.zeros(9), 9)
+    with pytest.raises(TypeError):
+        oracle.real_forward(np.zeros(8, dtype=np.complex64), 8)
+    with pytest.raises(ValueError):
+        oracle.real_inverse(np.zeros(6, dtype=np.complex128), 8)
