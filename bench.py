@@ -174,7 +174,8 @@ def main():
     ap.add_argument("--copy-reference", action="store_true",
                     help="also time a plain device copy of the same size")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "small", "uneven", "streamed", "serving"],
+                    choices=["large", "small", "uneven", "streamed", "serving", "long",
+                             "real", "frames"],
                     help="large = the 4096-point x 262144 batch (the reported metric); "
                          "the others print their own JSON line")
     ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")

@@ -1,5 +1,5 @@
 """The other workloads of bench.py (``--workload small|uneven|streamed|
-serving``).  Each prints one JSON line.  All inputs are seeded synthetic
+serving|long|real|frames``).  Each prints one JSON line.  All inputs are seeded synthetic
 signals (siggen); device buffers come from torch; every transform runs in
 libfftseg's kernels."""
 from __future__ import annotations
@@ -256,6 +256,98 @@ def serving(args):
     return 0
 
 
+def long(args):
+    """Four-step transforms resident in HBM: 8 GiB batches of 65536- and
+    2^20-point segments (the kernel side of the streamed workload)."""
+    import torch
+    import paper_1407_6915_amd as fs
+    total = 1 << 30
+    g = torch.Generator(device="cuda").manual_seed(0x14076915)
+    x = torch.randn(total, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    sh = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for n in (1 << 16, 1 << 20):
+        b = total // n
+        with fs.Plan(n, b) as p:
+            t = _time(torch, lambda: p.exec_ptr(x.data_ptr(), y.data_ptr(), sh), args.steps)
+            d = p.describe()
+        rows.append({"segment_len": n, "batch": b, "ms": round(t * 1e3, 3),
+                     "GFLOP/s": round(FLOP(n) * b / t / 1e9, 1),
+                     "algorithmic_GBps": round(16.0 * total / t / 1e9, 1),
+                     "two_pass_traffic_GBps": round(32.0 * total / t / 1e9, 1),
+                     "split": [d["n1"], d["n2"]],
+                     "tile_variants": [d["column_variant"], d["row_variant"]],
+                     "grid_mult": d["grid_mult"]})
+    print(json.dumps({"workload": "long_in_hbm", "rows": rows}), flush=True)
+    return 0
+
+
+def real(args):
+    """Real float32 segments (the 4-byte samples of the paper's records):
+    1024-point segments over 2^30 real samples (4 GiB in), forward to bins
+    0..512 and back, next to the complex transform of the same samples
+    stored as complex64 with zero imaginary parts."""
+    import torch
+    import paper_1407_6915_amd as fs
+    n, total = 1024, 1 << 30
+    b = total // n
+    g = torch.Generator(device="cuda").manual_seed(0x14076916)
+    x = torch.randn(total, dtype=torch.float32, device="cuda", generator=g)
+    spec = torch.empty(b * (n // 2 + 1), dtype=torch.complex64, device="cuda")
+    back = torch.empty_like(x)
+    sh = torch.cuda.current_stream().cuda_stream
+    fwd_bytes = b * (n * 4 + (n // 2 + 1) * 8)
+    with fs.RealPlan(n, b, fs.FORWARD) as pf, fs.RealPlan(n, b, fs.INVERSE) as pi:
+        tf = _time(torch, lambda: pf.exec_ptr(x.data_ptr(), spec.data_ptr(), sh), args.steps)
+        ti = _time(torch, lambda: pi.exec_ptr(spec.data_ptr(), back.data_ptr(), sh), args.steps)
+    del back
+    xc = x.to(torch.complex64)
+    yc = torch.empty_like(xc)
+    with fs.Plan(n, b) as pc:
+        tc = _time(torch, lambda: pc.exec_ptr(xc.data_ptr(), yc.data_ptr(), sh), args.steps)
+    print(json.dumps({"workload": "real_n1024_b1048576", "segment_len": n, "batch": b,
+                      "forward_ms": round(tf * 1e3, 3), "inverse_ms": round(ti * 1e3, 3),
+                      "forward_GBps": round(fwd_bytes / tf / 1e9, 1),
+                      "inverse_GBps": round(fwd_bytes / ti / 1e9, 1),
+                      "bytes_per_real_sample": round(fwd_bytes / total, 3),
+                      "complex_same_samples_ms": round(tc * 1e3, 3),
+                      "speedup_vs_complex": round(tc / tf, 2)}), flush=True)
+    return 0
+
+
+def frames(args):
+    """Short-time transform: 4096-point frames every 1024 samples (75 %
+    overlap) of a 2^28-sample signal with a periodic Hann window, next to
+    the plain transform of as many disjoint segments."""
+    import torch
+    import paper_1407_6915_amd as fs
+    n, hop, total = 4096, 1024, 1 << 28
+    nf = (total - n) // hop + 1
+    g = torch.Generator(device="cuda").manual_seed(0x14076917)
+    x = torch.randn(total, dtype=torch.complex64, device="cuda", generator=g)
+    j = torch.arange(n, dtype=torch.float64, device="cuda")
+    w = (0.5 - 0.5 * torch.cos(2 * math.pi * j / n)).float()
+    y = torch.empty(nf * n, dtype=torch.complex64, device="cuda")
+    sh = torch.cuda.current_stream().cuda_stream
+    with fs.Plan(n, nf) as p:
+        t = _time(torch, lambda: p.exec_frames_ptr(x.data_ptr(), total, y.data_ptr(), nf, hop,
+                                                   w.data_ptr(), sh), args.steps)
+        seg = total // n
+        t_plain = _time(torch, lambda: p.exec_ptr(x.data_ptr(), y.data_ptr(), sh, seg),
+                        args.steps)
+    out_bytes = nf * n * 8
+    print(json.dumps({"workload": "frames_n4096_hop1024_hann", "segment_len": n, "hop": hop,
+                      "frames": nf, "signal_samples": total, "ms": round(t * 1e3, 3),
+                      "GFLOP/s": round(FLOP(n) * nf / t / 1e9, 1),
+                      "frame_bytes_GBps": round(2 * out_bytes / t / 1e9, 1),
+                      "min_hbm_bytes_GBps": round((total * 8 + out_bytes) / t / 1e9, 1),
+                      "plain_segments_ms": round(t_plain * 1e3, 3),
+                      "plain_GBps": round(16.0 * seg * n / t_plain / 1e9, 1)}), flush=True)
+    return 0
+
+
 def run(args):
     return {"small": small, "uneven": uneven, "streamed": streamed,
-            "serving": serving}[args.workload](args)
+            "serving": serving, "long": long, "real": real,
+            "frames": frames}[args.workload](args)

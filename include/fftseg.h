@@ -83,6 +83,28 @@ typedef struct fftseg_plan *fft_plan_t;
  * FFT_ERR_UNSUPPORTED_LENGTH. */
 fft_plan_t fft_plan_create(size_t segment_len, size_t batch, int direction);
 
+/* Plan for real-input segments (the float32 samples of Sec. III, 4 bytes
+ * each).  segment_len = N must be even and N/2 a length with a one-pass
+ * kernel (N = 4 .. 32768 powers of two, 2000, 3072, 12000); otherwise
+ * FFT_ERR_UNSUPPORTED_LENGTH.  Executed by fft_exec_segments /
+ * fft_exec_segments_n, always out of place (in and out must not overlap,
+ * else FFT_ERR_OVERLAP):
+ *   FFT_FORWARD  in:  batch x N float32 (row s at byte offset s*N*4)
+ *                out: batch x (N/2+1) complex64, bins k = 0..N/2 of
+ *                     X_s[k] = sum_n x_s[n] exp(-2 pi i n k / N)
+ *                     (row s at byte offset s*(N/2+1)*8)
+ *   FFT_INVERSE  in:  batch x (N/2+1) complex64 bins 0..N/2
+ *                out: batch x N float32,
+ *                     x_s[n] = sum_{k<N} X_s[k] exp(+2 pi i n k / N)
+ *                     with X_s[N-k] = conj X_s[k], unnormalised; the
+ *                     imaginary parts of bins 0 and N/2 are ignored.
+ * Both buffers must be 8-byte aligned.  The N reals are transformed as
+ * N/2 complex values z[m] = x[2m] + i x[2m+1] by the one-pass kernel, with
+ * the split into even and odd parts fused into its store (forward) or
+ * load (inverse), so each byte crosses HBM once.  Streaming, frames, graph
+ * and work-list entry points take complex plans only. */
+fft_plan_t fft_plan_create_real(size_t segment_len, size_t batch, int direction);
+
 /* Transform every segment: the record at byte offset s*segment_len*8 of
  * `in` yields its spectrum at the same offset of `out`.  in == out (in
  * place) is allowed; any other overlap gives FFT_ERR_OVERLAP.  Each buffer
@@ -165,6 +187,43 @@ int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
                            void *const *host_in, int n_in,
                            void *const *host_out, int n_out, int n_slots,
                            fft_stream_stats_t *stats);
+
+/* Overlapping, optionally windowed segments: a short-time transform, the
+ * overlapping FFTs named as future work in Sec. VI.  Frame s
+ * (0 <= s < n_frames) is
+ *     x_s[j] = in[s*hop + j] * window[j],   0 <= j < segment_len,
+ * (window == NULL: all ones) and its spectrum is written at
+ * out + s*segment_len, natural order, same direction and scaling as
+ * fft_exec_segments.  hop < segment_len overlaps consecutive frames,
+ * hop == segment_len with no window is fft_exec_segments_n.
+ *   in      device, in_len complex64 samples; the frames read
+ *           (n_frames-1)*hop + segment_len of them (more -> FFT_ERR_BOUNDS)
+ *   out     device, n_frames*segment_len complex64; must not overlap in
+ *           (FFT_ERR_OVERLAP)
+ *   window  device, segment_len float32 values, 4-byte aligned, or NULL
+ * 1 <= n_frames <= the plan's batch and hop >= 1, else
+ * FFT_ERR_INVALID_ARG.  Lengths with a one-pass kernel read the frames in
+ * place; other lengths gather the windowed frames into out first and
+ * transform out in place. */
+int fft_exec_frames(fft_plan_t plan, const void *in, size_t in_len, void *out,
+                    size_t n_frames, size_t hop, const float *window, void *stream);
+
+/* File-backed streaming (Sec. III-IV: the signal lives in a file, the
+ * outputs are kept in input order).  Chunk c (c = first_chunk ..
+ * first_chunk + n_chunks - 1, each batch*segment_len*8 bytes) is read from
+ * byte in_offset + c*chunk_bytes of in_path and its spectra are written at
+ * byte out_offset + c*chunk_bytes of out_path (created if missing, never
+ * truncated), so every record keeps its offset and no merge step is needed.
+ * Reads and writes use io_threads parallel pread/pwrite calls per chunk,
+ * through the pipeline of fft_exec_stream.  A file shorter than the range
+ * gives FFT_ERR_BOUNDS before any device work; an I/O failure gives
+ * FFT_ERR_CALLBACK with *failed_chunk = the absolute chunk index (chunks
+ * below it are complete in out_path: rerun with first_chunk = that index to
+ * resume). */
+int fft_exec_file(fft_plan_t plan, const char *in_path, uint64_t in_offset,
+                  const char *out_path, uint64_t out_offset, uint64_t first_chunk,
+                  uint64_t n_chunks, int n_slots, int io_threads, uint64_t *failed_chunk,
+                  fft_stream_stats_t *stats);
 
 /* ------------------------------------------------------------------------
  * Uneven batches: one persistent launch over a work list (Sec. III batches

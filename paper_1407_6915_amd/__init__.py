@@ -92,10 +92,18 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         build()
+    # torch ships its own copy of the HIP runtime: load it first so that this
+    # library binds to the same copy (one HIP runtime per process; a second
+    # copy loaded later cannot open the GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, sz, i32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint64
     _sig(L, "fft_plan_create", vp, [sz, sz, i32])
     _sig(L, "fft_plan_create_variant", vp, [sz, sz, i32, i32])
+    _sig(L, "fft_plan_create_real", vp, [sz, sz, i32])
     _sig(L, "fft_variant_count", i32, [sz])
     _sig(L, "fft_split_info", i32, [sz, ctypes.POINTER(sz), ctypes.POINTER(sz),
                                     ctypes.POINTER(i32), ctypes.POINTER(i32)])
@@ -113,6 +121,9 @@ def lib():
     _sig(L, "fft_exec_stream_pinned", i32, [vp, u64, ctypes.POINTER(vp), i32,
                                             ctypes.POINTER(vp), i32, i32,
                                             ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_exec_file", i32, [vp, ctypes.c_char_p, u64, ctypes.c_char_p, u64, u64, u64,
+                                   i32, i32, ctypes.POINTER(u64), ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_exec_frames", i32, [vp, vp, sz, vp, sz, sz, vp, vp])
     _sig(L, "fft_worklist_supported", i32, [ctypes.c_uint32])
     _sig(L, "fft_worklist_create", vp, [ctypes.POINTER(WorkItem), sz, i32])
     _sig(L, "fft_worklist_reset", i32, [vp, ctypes.POINTER(WorkItem), sz, vp])
@@ -240,6 +251,38 @@ class Plan:
         self.exec_ptr(ip, op, _stream_handle(stream), batch)
         return out
 
+    def exec_frames_ptr(self, in_ptr: int, in_len: int, out_ptr: int, n_frames: int,
+                        hop: int, window_ptr: int = 0, stream: int = 0) -> None:
+        """fft_exec_frames on raw device pointers."""
+        _check(lib().fft_exec_frames(self.handle, in_ptr, in_len, out_ptr, n_frames, hop,
+                                     window_ptr or None, stream))
+
+    def exec_frames(self, x, hop: int, n_frames: Optional[int] = None, window=None,
+                    out=None, stream=None):
+        """Short-time transform: frame s starts at sample s*hop of the
+        complex64 GPU tensor x and is multiplied by ``window`` (a float32
+        GPU tensor of segment_len values, or None) before its transform.
+        n_frames defaults to every whole frame x holds, capped at the
+        plan's batch.  Returns ``out`` ([n_frames * segment_len])."""
+        import torch
+        n = self.segment_len
+        total = x.numel()
+        if n_frames is None:
+            n_frames = min(self.batch, (total - n) // hop + 1 if total >= n else 0)
+        ip = _tensor_ptr(x, 0, "x")
+        wp = 0
+        if window is not None:
+            if window.dtype != torch.float32 or not window.is_cuda or not window.is_contiguous():
+                raise TypeError("window must be a contiguous float32 GPU tensor")
+            if window.numel() != n:
+                raise ValueError("window holds %d values, %d needed" % (window.numel(), n))
+            wp = window.data_ptr()
+        if out is None:
+            out = torch.empty(max(n_frames, 0) * n, dtype=torch.complex64, device=x.device)
+        op = _tensor_ptr(out, n_frames * n, "out")
+        self.exec_frames_ptr(ip, total, op, n_frames, hop, wp, _stream_handle(stream))
+        return out
+
     def exec_stream(self, n_chunks: int, fill, drain=None, n_slots: int = 3):
         """Stream n_chunks chunks of this plan's batch through the GPU.
 
@@ -274,6 +317,23 @@ class Plan:
         st = StreamStats()
         rc = lib().fft_exec_stream(self.handle, n_chunks, f_fill, f_drain, uptr,
                                    n_slots, ctypes.byref(failed), ctypes.byref(st))
+        if rc < 0 and rc != -7:
+            raise FFTError(rc, last_error())
+        fc = None if failed.value == 2 ** 64 - 1 else int(failed.value)
+        return rc, fc, st.as_dict()
+
+    def exec_file(self, in_path: str, out_path: str, n_chunks: int, first_chunk: int = 0,
+                  in_offset: int = 0, out_offset: int = 0, n_slots: int = 3,
+                  io_threads: int = 8):
+        """Stream chunks of a signal file through the GPU, spectra written
+        at the same relative offsets of out_path.  Returns (status,
+        failed_chunk or None, stats); an I/O failure is reported in the
+        status, other errors raise."""
+        failed = ctypes.c_uint64(0)
+        st = StreamStats()
+        rc = lib().fft_exec_file(self.handle, in_path.encode(), in_offset, out_path.encode(),
+                                 out_offset, first_chunk, n_chunks, n_slots, io_threads,
+                                 ctypes.byref(failed), ctypes.byref(st))
         if rc < 0 and rc != -7:
             raise FFTError(rc, last_error())
         fc = None if failed.value == 2 ** 64 - 1 else int(failed.value)
@@ -317,6 +377,51 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class RealPlan(Plan):
+    """Plan for ``batch`` real segments of even length ``segment_len``.
+
+    Forward: float32 [batch * N] -> complex64 [batch * (N/2+1)] (bins
+    0..N/2 of every segment).  Inverse: complex64 bins -> float32 samples,
+    unnormalised.  Always out of place.
+    """
+
+    def __init__(self, segment_len: int, batch: int, direction: int = FORWARD):
+        L = lib()
+        h = L.fft_plan_create_real(segment_len, batch, direction)
+        if not h:
+            raise FFTError(L.fft_last_status(), last_error())
+        self._h = h
+        self.segment_len = segment_len
+        self.batch = batch
+        self.direction = direction
+
+    @property
+    def bins(self) -> int:
+        return self.segment_len // 2 + 1
+
+    def exec(self, x, out=None, stream=None, batch: Optional[int] = None):
+        import torch
+        b = self.batch if batch is None else batch
+        real_n, cplx_n = b * self.segment_len, b * self.bins
+        if self.direction == FORWARD:
+            in_dt, out_dt, need_in, need_out = torch.float32, torch.complex64, real_n, cplx_n
+        else:
+            in_dt, out_dt, need_in, need_out = torch.complex64, torch.float32, cplx_n, real_n
+        for t, dt, need, name in ((x, in_dt, need_in, "x"), (out, out_dt, need_out, "out")):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or t.dtype != dt:
+                raise TypeError("%s must be a %s tensor" % (name, dt))
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous GPU tensor" % name)
+            if t.numel() < need:
+                raise ValueError("%s holds %d values, %d needed" % (name, t.numel(), need))
+        if out is None:
+            out = torch.empty(need_out, dtype=out_dt, device=x.device)
+        self.exec_ptr(x.data_ptr(), out.data_ptr(), _stream_handle(stream), batch)
+        return out
 
 
 class WorkList:

@@ -8,8 +8,9 @@ namespace {
 
 // flag bits: streamed global access; twiddles reloaded per tile (all
 // stages, or all but the last); XCD-aware tile order; register allocation
-// for 2 waves per SIMD
-constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16;
+// for 2 waves per SIMD; lane index kept across the tiles of the persistent
+// loop
+constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -21,7 +22,7 @@ template <int M, int T, int C, int PS, int F, int... Rs>
 struct ColInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
     using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
-                             (F & kXcd) != 0, (F & kW2) ? 2 : 1>;
+                             (F & kXcd) != 0, (F & kW2) ? 2 : 1, (F & kPlainLane) != 0>;
     static void launch(int dir, const void *in, void *ybuf, const void *tw,
                        const void *tl, const void *th, int sh, int n2,
                        uint64_t batch, unsigned grid, hipStream_t s)
@@ -60,7 +61,7 @@ template <int M, int T, int C, int PS, int F, int... Rs>
 struct RowInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
     using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
-                          (F & kXcd) != 0, (F & kW2) ? 2 : 1>;
+                          (F & kXcd) != 0, (F & kW2) ? 2 : 1, (F & kPlainLane) != 0>;
     static void launch(int dir, const void *ybuf, void *out, const void *tw, int n1,
                        uint64_t batch, unsigned grid, hipStream_t s)
     {
@@ -97,13 +98,18 @@ struct RowInst {
 const ColumnDesc kColumns[] = {
     ColInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
     ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
+    ColInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
     ColInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
     ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
+    ColInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
+    ColInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
     ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
+    ColInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(2),
     ColInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
@@ -111,20 +117,29 @@ const ColumnDesc kColumns[] = {
     ColInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
     ColInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
     ColInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),
+    ColInst<1024, 64, 8, 4, kXcd | kPlainLane, 16, 16, 4>::desc(7),
+    ColInst<1024, 64, 8, 4, kNT | kXcd | kPlainLane, 16, 16, 4>::desc(8),
+    ColInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(9),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),
 };
 
 const RowDesc kRows[] = {
     RowInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
     RowInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
+    RowInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
     RowInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
     RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
     RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
+    RowInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
+    RowInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
+    RowInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
     RowInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
+    RowInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(2),
     RowInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
     RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
     RowInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
@@ -132,8 +147,12 @@ const RowDesc kRows[] = {
     RowInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
     RowInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
     RowInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),
+    RowInst<1024, 64, 8, 4, kXcd | kPlainLane, 16, 16, 4>::desc(7),
+    RowInst<1024, 64, 8, 4, kNT | kXcd | kPlainLane, 16, 16, 4>::desc(8),
+    RowInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(9),
     RowInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
+    RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),
 };
 
 template <int R>

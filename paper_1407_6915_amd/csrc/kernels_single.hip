@@ -13,8 +13,13 @@ namespace {
 // every stage reloads its twiddles per segment; kHoistLast = only the last
 // stage keeps its twiddles in registers across segments (default: all
 // stages do); kW2 / kW3 = the register allocation must allow 2 / 3 waves
-// per SIMD.
-constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16;
+// per SIMD; kPlainLane / kPlainLds = the lane index is kept across the
+// segments of the persistent loop / LDS addresses are computed per access;
+// kClassic = the plainly written kernel (see SinglePassPolicy); kAux = this
+// row also provides the length's frame (overlapping segment) and
+// real-input kernels (one row per length).
+constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
+              kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -31,18 +36,53 @@ template <int N, int T, int S, int PS, int F, int... Rs>
 struct SpInst {
     using Sh = Shape<N, T, Radices<Rs...>>;
     using Pol = SinglePassPolicy<Sh, S, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
-                                 false, waves<F>()>;
+                                 false, waves<F>(), (F & kPlainLane) != 0,
+                                 (F & kPlainLds) != 0, (F & kClassic) != 0>;
 
+    using kernel_fn = void (*)(const c32 *, c32 *, const c32 *, uint64_t);
+    template <int D>
+    static constexpr kernel_fn kernel()
+    {
+        if constexpr ((F & kClassic) != 0)
+            return &single_pass_plain_kernel<Sh, Pol, D>;
+        else
+            return &single_pass_kernel<Sh, Pol, D>;
+    }
     static void launch(int dir, const void *in, void *out, const void *tw,
                        uint64_t batch, unsigned grid, hipStream_t s)
     {
         const dim3 g(grid), b(Pol::kThreads);
         if (dir < 0)
-            hipLaunchKernelGGL((single_pass_kernel<Sh, Pol, -1>), g, b, 0, s,
-                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch);
+            hipLaunchKernelGGL(kernel<-1>(), g, b, 0, s, (const c32 *)in, (c32 *)out,
+                               (const c32 *)tw, batch);
         else
-            hipLaunchKernelGGL((single_pass_kernel<Sh, Pol, 1>), g, b, 0, s,
-                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch);
+            hipLaunchKernelGGL(kernel<1>(), g, b, 0, s, (const c32 *)in, (c32 *)out,
+                               (const c32 *)tw, batch);
+    }
+    static void launch_strided(int dir, const void *in, void *out, const void *tw,
+                               uint64_t batch, uint64_t in_stride, uint64_t out_stride,
+                               const float *window, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch, in_stride,
+                               out_stride, window);
+        else
+            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch, in_stride,
+                               out_stride, window);
+    }
+    static void launch_real(int dir, const void *in, void *out, const void *tw, const void *hw,
+                            uint64_t batch, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((real_forward_kernel<Sh, Pol>), g, b, 0, s, (const c32 *)in,
+                               (c32 *)out, (const c32 *)tw, (const c32 *)hw, batch);
+        else
+            hipLaunchKernelGGL((real_inverse_kernel<Sh, Pol>), g, b, 0, s, (const c32 *)in,
+                               (c32 *)out, (const c32 *)tw, (const c32 *)hw, batch);
     }
     static SinglePassDesc desc(int variant, int grid_mult)
     {
@@ -61,8 +101,16 @@ struct SpInst {
         for (int i = 0; i < d.nrad; ++i)
             d.radices[i] = r[i];
         d.launch = &launch;
-        d.kernel[0] = (const void *)&single_pass_kernel<Sh, Pol, -1>;
-        d.kernel[1] = (const void *)&single_pass_kernel<Sh, Pol, 1>;
+        d.kernel[0] = (const void *)kernel<-1>();
+        d.kernel[1] = (const void *)kernel<1>();
+        if constexpr ((F & kAux) != 0) {
+            d.launch_strided = &launch_strided;
+            d.kernel_strided[0] = (const void *)&single_pass_strided_kernel<Sh, Pol, -1>;
+            d.kernel_strided[1] = (const void *)&single_pass_strided_kernel<Sh, Pol, 1>;
+            d.launch_real = &launch_real;
+            d.kernel_real[0] = (const void *)&real_forward_kernel<Sh, Pol>;
+            d.kernel_real[1] = (const void *)&real_inverse_kernel<Sh, Pol>;
+        }
         return d;
     }
 };
@@ -72,55 +120,58 @@ struct SpInst {
 // grid (0: one workgroup per tile).
 //                 N      T    S  PS  F              radices     variant, grid_mult
 const SinglePassDesc kTable[] = {
-    SpInst<2, 1, 64, 0, kNT, 2>::desc(0, 0),
-    SpInst<4, 1, 64, 0, kNT, 4>::desc(0, 0),
-    SpInst<8, 1, 64, 0, kNT, 8>::desc(0, 0),
-    SpInst<16, 1, 64, 0, kNT, 16>::desc(0, 0),
-    SpInst<32, 4, 32, 4, kNT, 8, 4>::desc(0, 0),
-    SpInst<64, 8, 32, 4, kNT, 8, 8>::desc(0, 0),
-    SpInst<128, 8, 32, 4, kNT, 16, 8>::desc(0, 0),
-    SpInst<256, 16, 8, 4, kNT, 16, 16>::desc(0, 32),
-    SpInst<256, 16, 8, 4, 0, 16, 16>::desc(1, 0),
-    SpInst<256, 16, 16, 4, 0, 16, 16>::desc(2, 0),
-    SpInst<512, 64, 4, 4, kNT, 8, 8, 8>::desc(0, 16),
-    SpInst<512, 32, 8, 4, kNT, 16, 16, 2>::desc(1, 16),
-    SpInst<1024, 64, 4, 4, kNT, 16, 16, 4>::desc(0, 0),
-    SpInst<1024, 64, 4, 4, 0, 16, 16, 4>::desc(1, 0),
-    SpInst<1024, 64, 4, 4, 0, 4, 16, 16>::desc(2, 32),
-    SpInst<1024, 128, 2, 4, 0, 8, 8, 16>::desc(3, 32),
-    SpInst<1024, 64, 2, 4, kNT, 16, 16, 4>::desc(4, 32),
-    SpInst<2048, 128, 2, 4, kNT, 16, 16, 8>::desc(0, 16),
-    SpInst<2048, 128, 1, 4, kNT, 16, 16, 8>::desc(1, 16),
-    SpInst<2048, 64, 2, 4, kNT, 16, 16, 8>::desc(2, 16),
-    SpInst<4096, 128, 2, 4, kNT | kHoistLast | kW2, 16, 16, 16>::desc(0, 32),
-    SpInst<4096, 128, 2, 4, kNT | kNoHoist | kW2, 16, 16, 16>::desc(1, 32),
-    SpInst<4096, 128, 2, 4, kNT | kW2, 16, 16, 16>::desc(2, 32),
-    SpInst<4096, 128, 2, 4, kNT, 16, 16, 16>::desc(3, 32),
-    SpInst<4096, 256, 1, 4, kNT, 16, 16, 16>::desc(4, 32),
-    SpInst<4096, 256, 1, 0, kNT, 16, 16, 16>::desc(5, 32),
-    SpInst<4096, 512, 1, 4, kNT, 8, 8, 8, 8>::desc(6, 32),
-    SpInst<4096, 256, 1, 4, kNT | kHoistLast | kW3, 16, 16, 16>::desc(7, 32),
-    SpInst<8192, 512, 1, 4, kNT, 16, 16, 16, 2>::desc(0, 4),
-    SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(1, 4),
-    SpInst<8192, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 2>::desc(2, 4),
-    SpInst<8192, 512, 1, 4, kNT | kHoistLast | kW2, 16, 16, 16, 2>::desc(3, 8),
-    SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(0, 8),
-    SpInst<16384, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(1, 8),
-    SpInst<16384, 1024, 1, 4, kNoHoist, 16, 16, 16, 4>::desc(2, 8),
-    SpInst<16384, 1024, 1, 0, kNT | kNoHoist, 16, 16, 16, 4>::desc(3, 8),
+    SpInst<2, 1, 64, 0, kNT | kPlain | kAux, 2>::desc(0, 0),
+    SpInst<4, 1, 64, 0, kNT | kPlain | kAux, 4>::desc(0, 0),
+    SpInst<8, 1, 64, 0, kNT | kPlain | kAux, 8>::desc(0, 0),
+    SpInst<16, 1, 64, 0, kNT | kPlain | kAux, 16>::desc(0, 0),
+    SpInst<32, 4, 32, 4, kNT | kPlain | kAux, 8, 4>::desc(0, 0),
+    SpInst<64, 8, 32, 4, kNT | kPlain | kAux, 8, 8>::desc(0, 0),
+    SpInst<128, 8, 32, 4, kNT | kPlain | kAux, 16, 8>::desc(0, 0),
+    SpInst<256, 16, 8, 4, kPlain | kAux, 16, 16>::desc(0, 0),
+    SpInst<256, 16, 8, 4, kNT | kPlain, 16, 16>::desc(1, 32),
+    SpInst<256, 16, 8, 4, kNT, 16, 16>::desc(2, 32),
+    SpInst<256, 16, 8, 4, kClassic | kNT, 16, 16>::desc(3, 64),
+    SpInst<512, 64, 4, 4, kNT | kPlain | kAux, 8, 8, 8>::desc(0, 0),
+    SpInst<512, 64, 4, 4, kPlain, 8, 8, 8>::desc(1, 32),
+    SpInst<512, 32, 8, 4, kNT | kPlain, 16, 16, 2>::desc(2, 64),
+    SpInst<1024, 64, 2, 4, kNT | kPlain | kAux, 16, 16, 4>::desc(0, 64),
+    SpInst<1024, 64, 4, 4, kNT | kPlain, 16, 16, 4>::desc(1, 64),
+    SpInst<1024, 64, 4, 4, kPlain, 16, 16, 4>::desc(2, 32),
+    SpInst<1024, 64, 4, 4, kNT, 16, 16, 4>::desc(3, 32),
+    SpInst<1024, 64, 4, 4, kClassic, 16, 16, 4>::desc(4, 32),
+    SpInst<2048, 128, 1, 4, kNT | kPlain | kAux, 16, 16, 8>::desc(0, 64),
+    SpInst<2048, 128, 2, 4, kNT | kPlain, 16, 16, 8>::desc(1, 64),
+    SpInst<2048, 128, 2, 4, kPlain, 16, 16, 8>::desc(2, 32),
+    SpInst<2048, 128, 2, 4, kClassic, 16, 16, 8>::desc(3, 32),
+    SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 32),
+    SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
+    SpInst<4096, 512, 1, 4, kNT | kPlain | kAux, 8, 8, 8, 8>::desc(2, 64),
+    SpInst<4096, 256, 1, 0, kNT | kPlain, 16, 16, 16>::desc(3, 32),
+    SpInst<4096, 128, 2, 0, kNT | kPlain, 16, 16, 16>::desc(4, 32),
+    SpInst<4096, 256, 1, 4, kPlain, 16, 16, 16>::desc(5, 32),
+    SpInst<4096, 256, 1, 0, kClassic | kNT, 16, 16, 16>::desc(6, 32),
+    SpInst<4096, 512, 1, 4, kClassic | kNT, 8, 8, 8, 8>::desc(7, 32),
+    SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(0, 32),
+    SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(1, 32),
+    SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(2, 32),
+    SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(3, 32),
+    SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(0, 32),
+    SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(1, 32),
+    SpInst<16384, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),
+    SpInst<16384, 1024, 1, 4, kClassic | kNT, 16, 16, 16, 4>::desc(3, 32),
     // mixed radix 2/3/5
-    SpInst<1000, 100, 2, 4, kNT, 10, 10, 10>::desc(0, 32),
-    SpInst<1000, 100, 2, 4, 0, 10, 10, 10>::desc(1, 32),
-    SpInst<1000, 125, 2, 4, kNT, 8, 5, 5, 5>::desc(2, 32),
-    SpInst<1000, 200, 1, 4, kNT, 5, 5, 5, 8>::desc(3, 32),
-    SpInst<1536, 96, 2, 4, kNT, 16, 16, 6>::desc(0, 32),
-    SpInst<1536, 96, 2, 4, 0, 16, 16, 6>::desc(1, 32),
-    SpInst<1536, 192, 1, 4, kNT, 8, 8, 8, 3>::desc(2, 32),
-    SpInst<6000, 400, 1, 4, kNT, 16, 15, 25>::desc(0, 16),
-    SpInst<6000, 400, 1, 4, 0, 16, 15, 25>::desc(1, 16),
-    SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(2, 0),
-    SpInst<6000, 300, 1, 4, kNT | kNoHoist, 20, 20, 15>::desc(3, 0),
-    SpInst<6000, 400, 1, 4, kNT | kHoistLast | kW2, 16, 15, 25>::desc(4, 16),
+    SpInst<1000, 100, 2, 4, kClassic, 10, 10, 10>::desc(0, 64),
+    SpInst<1000, 100, 2, 4, kPlain, 10, 10, 10>::desc(1, 64),
+    SpInst<1000, 100, 2, 4, kNT | kPlain | kAux, 10, 10, 10>::desc(2, 32),
+    SpInst<1000, 125, 2, 4, kNT | kPlain, 8, 5, 5, 5>::desc(3, 32),
+    SpInst<1536, 96, 2, 4, kNT | kPlain | kAux, 16, 16, 6>::desc(0, 64),
+    SpInst<1536, 96, 2, 4, kPlain, 16, 16, 6>::desc(1, 32),
+    SpInst<1536, 96, 2, 4, kNT, 16, 16, 6>::desc(2, 32),
+    SpInst<1536, 96, 2, 4, kClassic | kNT, 16, 16, 6>::desc(3, 64),
+    SpInst<6000, 400, 1, 4, kClassic | kNT, 16, 15, 25>::desc(0, 32),
+    SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(1, 0),
+    SpInst<6000, 300, 1, 4, kNT | kNoHoist | kAux, 20, 20, 15>::desc(2, 32),
+    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kPlain, 16, 15, 25>::desc(3, 32),
 };
 
 }  // namespace

@@ -10,6 +10,12 @@ constexpr int kMaxRadices = 12;
 
 using sp_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
                               uint64_t batch, unsigned grid, hipStream_t s);
+using sp_strided_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
+                                      uint64_t batch, uint64_t in_stride, uint64_t out_stride,
+                                      const float *window, unsigned grid, hipStream_t s);
+using sp_real_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
+                                   const void *hw, uint64_t batch, unsigned grid,
+                                   hipStream_t s);
 using col_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
                                const void *tl, const void *th, int sh, int n2,
                                uint64_t batch, unsigned grid, hipStream_t s);
@@ -31,6 +37,10 @@ struct SinglePassDesc {
     int radices[kMaxRadices];
     sp_launch_fn launch;
     const void *kernel[2];  // [0] forward, [1] inverse (occupancy queries)
+    sp_strided_launch_fn launch_strided;  // overlapping/windowed segments (variant 0)
+    const void *kernel_strided[2];
+    sp_real_launch_fn launch_real;  // real segments of length 2n (variant 0)
+    const void *kernel_real[2];     // [0] forward (real in), [1] inverse (real out)
 };
 
 // Four-step pass A: N1-point column transforms, C columns per workgroup.

@@ -201,6 +201,17 @@ const SinglePassDesc *find_single(uint64_t n, int variant)
     return nullptr;
 }
 
+// the variant of length n that carries the frame and real-input kernels
+const SinglePassDesc *find_aux(uint64_t n)
+{
+    int cnt = 0;
+    const SinglePassDesc *t = single_pass_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if ((uint64_t)t[i].n == n && t[i].launch_strided && t[i].launch_real)
+            return &t[i];
+    return nullptr;
+}
+
 int variant_count(uint64_t n)
 {
     int cnt = 0, k = 0;
@@ -421,6 +432,41 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
     return set_ok();
 }
 
+int plan_build_real(Plan *p, uint64_t n, uint64_t batch, int dir)
+{
+    p->n = n;
+    p->batch = batch;
+    p->dir = dir;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_HIP, "no HIP device available");
+    }
+    const uint64_t m = n / 2;
+    p->sp = find_aux(m);
+    if (!p->sp || !p->sp->launch_real)
+        return set_error(FFT_ERR_UNSUPPORTED_LENGTH,
+                         "real segments of length %llu need a one-pass kernel of length %llu",
+                         (unsigned long long)n, (unsigned long long)m);
+    p->kind = Plan::REAL;
+    p->grid_mult = p->sp->grid_mult;
+    std::vector<c32> hw(m + 1);
+    for (uint64_t k = 0; k <= m; ++k)
+        hw[k] = root_forward(k, n);
+    hipError_t e;
+    if ((e = upload(root_table(m), &p->tw)) != hipSuccess || (e = upload(hw, &p->tw2)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                        : hip_error(e, "twiddle upload");
+    return set_ok();
+}
+
+int reject_real(const Plan *p, const char *what)
+{
+    if (p && p->kind == Plan::REAL)
+        return set_error(FFT_ERR_INVALID_ARG, "%s takes complex plans; real plans run through"
+                         " fft_exec_segments", what);
+    return FFT_OK;
+}
+
 void plan_free(Plan *p)
 {
     if (p->used && p->last_stream_valid)
@@ -509,6 +555,14 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
         const unsigned grid = grid_for(d->kernel[dir > 0], d->threads * d->segs_per_wg,
                                        groups, p->device, p->grid_mult);
         d->launch(dir, in, out, p->tw, batch, grid, s);
+        break;
+    }
+    case Plan::REAL: {
+        const SinglePassDesc *d = p->sp;
+        const uint64_t groups = (batch + d->segs_per_wg - 1) / d->segs_per_wg;
+        const unsigned grid = grid_for(d->kernel_real[dir > 0], d->threads * d->segs_per_wg,
+                                       groups, p->device, p->grid_mult);
+        d->launch_real(dir, in, out, p->tw, p->tw2, batch, grid, s);
         break;
     }
     case Plan::FOURSTEP: {
@@ -607,6 +661,15 @@ int plan_describe(const Plan *p, std::string &js)
                  p->col->variant, p->row->variant, p->grid_mult,
                  p->col->lds_bytes, p->row->lds_bytes, (unsigned long long)p->sub_batch,
                  p->scratch_bytes);
+        break;
+    case Plan::REAL:
+        snprintf(buf, sizeof buf,
+                 "{\"kind\":\"real\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
+                 "\"complex_length\":%llu,\"radices\":%s,\"threads_per_segment\":%d,"
+                 "\"segments_per_workgroup\":%d,\"grid_mult\":%d,\"scratch_bytes\":0}",
+                 (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
+                 (unsigned long long)(p->n / 2), rad(p->sp->radices, p->sp->nrad).c_str(),
+                 p->sp->threads, p->sp->segs_per_wg, p->grid_mult);
         break;
     case Plan::GENERIC:
         snprintf(buf, sizeof buf,
@@ -721,6 +784,29 @@ extern "C" fft_plan_t fft_plan_create_variant(size_t segment_len, size_t batch,
     FFT_GUARD_END(nullptr)
 }
 
+extern "C" fft_plan_t fft_plan_create_real(size_t segment_len, size_t batch, int direction)
+{
+    FFT_GUARD_BEGIN
+    if (validate_create(segment_len, batch, direction) != FFT_OK)
+        return nullptr;
+    if (segment_len < 4 || segment_len % 2) {
+        set_error(FFT_ERR_UNSUPPORTED_LENGTH, "real segments need an even length >= 4 (got %zu)",
+                  segment_len);
+        return nullptr;
+    }
+    Plan *p = new Plan();
+    if (plan_build_real(p, segment_len, batch, direction) != FFT_OK) {
+        const int st = last_status();
+        std::string msg = last_message();
+        plan_free(p);
+        delete p;
+        set_error(st, "%s", msg.c_str());
+        return nullptr;
+    }
+    return reinterpret_cast<fft_plan_t>(p);
+    FFT_GUARD_END(nullptr)
+}
+
 extern "C" int fft_split_info(size_t n, size_t *n1, size_t *n2, int *ncol, int *nrow)
 {
     FFT_GUARD_BEGIN
@@ -779,10 +865,29 @@ extern "C" int fft_exec_segments_n(fft_plan_t plan, const void *in, void *out,
     if (batch == 0 || batch > p->batch)
         return set_error(FFT_ERR_INVALID_ARG, "batch %zu outside [1, %llu]", batch,
                          (unsigned long long)p->batch);
-    const uint64_t bytes = (uint64_t)batch * p->n * sizeof(c32);
-    int st = check_io(in, out, bytes);
-    if (st != FFT_OK)
-        return st;
+    int st;
+    if (p->kind == Plan::REAL) {
+        // forward: n floats in, n/2+1 complex out; inverse the other way round
+        const uint64_t rb = (uint64_t)batch * p->n * sizeof(float);
+        const uint64_t cb = (uint64_t)batch * (p->n / 2 + 1) * sizeof(c32);
+        const uint64_t ib = p->dir < 0 ? rb : cb, ob = p->dir < 0 ? cb : rb;
+        if (!in || !out)
+            return set_error(FFT_ERR_INVALID_ARG, "in/out must not be NULL");
+        if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
+            return set_error(FFT_ERR_ALIGNMENT, "in/out must be 8-byte aligned");
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        if (a < b + ob && b < a + ib)
+            return set_error(FFT_ERR_OVERLAP, "real transforms run out of place: in and out"
+                             " overlap");
+        if ((st = check_device_range(in, ib, "in")) != FFT_OK ||
+            (st = check_device_range(out, ob, "out")) != FFT_OK)
+            return st;
+    } else {
+        const uint64_t bytes = (uint64_t)batch * p->n * sizeof(c32);
+        st = check_io(in, out, bytes);
+        if (st != FFT_OK)
+            return st;
+    }
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess)
         return hip_error(hipGetLastError(), "hipGetDevice");

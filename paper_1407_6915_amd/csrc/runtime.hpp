@@ -14,7 +14,7 @@
 namespace fftseg {
 
 struct Plan {
-    enum Kind { COPY, SINGLE, FOURSTEP, GENERIC };
+    enum Kind { COPY, SINGLE, FOURSTEP, GENERIC, REAL };
     uint64_t n = 0, batch = 0;
     int dir = -1;
     int device = 0;
@@ -25,7 +25,7 @@ struct Plan {
     uint64_t n1 = 0, n2 = 0;
     std::vector<int> radices;   // fallback path
     void *tw = nullptr;         // W_N (single pass) or W_N1 (four-step) table
-    void *tw2 = nullptr;        // W_N2 table (four-step)
+    void *tw2 = nullptr;        // W_N2 table (four-step); W_N^k, k <= N/2 (real)
     void *tl = nullptr, *th = nullptr;  // two-level W_N table
     int sh = 0;
     void *scratch = nullptr;
@@ -52,6 +52,7 @@ const char *last_message();
 
 c32 root_forward(uint64_t m, uint64_t n);
 const SinglePassDesc *find_single(uint64_t n, int variant);
+const SinglePassDesc *find_aux(uint64_t n);
 int variant_count(uint64_t n);
 bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,
                 int row_variant);
@@ -66,6 +67,10 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
                int forced_split_variants = -1);
 void plan_free(Plan *p);
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
+// real-input plans: length n = 2m through the m-point one-pass kernel
+int plan_build_real(Plan *p, uint64_t n, uint64_t batch, int dir);
+// entry points that only take complex segments refuse real plans
+int reject_real(const Plan *p, const char *what);
 int plan_describe(const Plan *p, std::string &js);
 int check_io(const void *in, const void *out, uint64_t bytes);
 int check_device_range(const void *ptr, uint64_t bytes, const char *name);

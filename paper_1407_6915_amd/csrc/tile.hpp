@@ -164,7 +164,7 @@ template <class Pol, int STEP, int R>
 struct LdsRun {
     static constexpr bool kStrided = Pol::template strided<STEP>();
     static constexpr bool kUnitRun = (STEP == 1) && Pol::template unit_run<R>();
-    static constexpr bool kSep = kStrided || kUnitRun;
+    static constexpr bool kSep = (kStrided || kUnitRun) && !Pol::kPlainLds;
     static constexpr int kStride = kStrided ? Pol::template stride<STEP>() : Pol::template stride<1>();
 };
 
@@ -199,7 +199,7 @@ __device__ __forceinline__ void lds_gather(c32 *v, int t, int c, const c32 *lds)
     for (int u = 0; u < St::U; ++u) {
         const int b = t + u * Sh::T;
         if (St::kFull || b < St::NB) {
-            if constexpr (Run::kStrided) {
+            if constexpr (Run::kStrided && !Pol::kPlainLds) {
                 const c32 *p = lds + Pol::lds(c, b);
 #pragma unroll
                 for (int r = 0; r < St::R; ++r)
@@ -248,6 +248,32 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
     }
 }
 
+// The same stages written plainly: every LDS access computes its own padded
+// address and the compiler is left to keep whatever it hoists in registers
+// (single_pass_plain_kernel also computes the lane mapping once, outside
+// its persistent loop).
+template <class Sh, class Pol, int D, int I, int L>
+__device__ __forceinline__ void tile_run_plain(c32 *v, c32 *lds, const c32 *__restrict__ tw,
+                                               int tid, const typename Pol::Ctx &ctx)
+{
+    using St = Stage<Sh, I, L>;
+    const int c = Pol::template col<I>(tid);
+    const int t = Pol::template thr<I>(tid);
+    st_compute<St, Sh, L, D>(v, t, tw);
+    if constexpr (St::kLast) {
+        Pol::template store<St, D>(v, t, c, ctx);
+    } else {
+        st_scatter<St, Sh, L>(v, t, [&](int i, c32 a) { lds[Pol::lds(c, i)] = a; });
+        __syncthreads();
+        using Nx = Stage<Sh, I + 1, L * St::R>;
+        const int c2 = Pol::template col<I + 1>(tid);
+        const int t2 = Pol::template thr<I + 1>(tid);
+        st_gather<Nx, Sh>(v, t2, [&](int i) { return lds[Pol::lds(c2, i)]; });
+        __syncthreads();
+        tile_run_plain<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, ctx);
+    }
+}
+
 // a copy of the lane index the compiler cannot treat as loop-invariant
 __device__ __forceinline__ int opaque_lane()
 {
@@ -265,10 +291,19 @@ __device__ __forceinline__ int opaque_lane()
 // twiddles in registers across the segments of a persistent loop.  Waves =
 // the waves per SIMD the register allocation must allow.)
 template <class Sh, int S_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Partial_ = false, int Waves_ = 1>
+          bool Partial_ = false, int Waves_ = 1, bool PlainLane_ = false,
+          bool PlainLds_ = false, bool Classic_ = false>
 struct SinglePassPolicy {
     static constexpr int S = S_;
     static constexpr int PS = PS_;
+    // PlainLane: the persistent loop keeps the lane index (and what the
+    // compiler derives from it) across segments instead of recomputing it;
+    // PlainLds: every LDS access computes its padded address on its own;
+    // Classic: the stages run through tile_run_plain (both of the above,
+    // and no per-stage choices left to the policy)
+    static constexpr bool kPlainLane = PlainLane_ || Classic_;
+    static constexpr bool kPlainLds = PlainLds_;
+    static constexpr bool kClassic = Classic_;
     static constexpr bool kNT = NT_;
     static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kPartial = Partial_;
@@ -332,6 +367,74 @@ __device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw
     tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
+// Overlapping, windowed segments (short-time transform): segment s reads
+// x_s[n] = in[s * in_stride + n] * window[n] (window may be null) and writes
+// its spectrum at out + s * out_stride.
+template <class Sh, class Pol, int D>
+__device__ __forceinline__ void windowed_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
+                                              int tid_tw, const c32 *x, c32 *y, bool valid,
+                                              const float *__restrict__ window)
+{
+    const int t = Pol::template thr<0>(tid);
+    typename Pol::Ctx ctx{y, valid && Pol::active(tid)};
+    c32 v[Sh::kMaxE];
+    using S0 = Stage<Sh, 0, 1>;
+    if (ctx.valid) {
+        if (window) {
+            st_gather<S0, Sh>(v, t, [&](int i) {
+                const c32 a = gload<Pol::kNT>(x + i);
+                const float w = window[i];
+                return c32{a.x * w, a.y * w};
+            });
+        } else {
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        }
+    }
+    if constexpr (Pol::kClassic)
+        tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    else
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+}
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    single_pass_strided_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                               uint64_t batch, uint64_t in_stride, uint64_t out_stride,
+                               const float *__restrict__ window)
+{
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int tid_tw = threadIdx.x;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+        const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+        windowed_tile<Sh, Pol, D>(lds, tw, tid, tid_tw, in + seg * in_stride,
+                                  out + seg * out_stride, seg < batch, window);
+    }
+}
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads)
+    single_pass_plain_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                             uint64_t batch)
+{
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int tid = threadIdx.x;
+    const int slot = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const uint64_t seg = g * Pol::S + slot;
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch};
+        const c32 *x = in + seg * Sh::M;
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        if (ctx.valid)
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
 template <class Sh, class Pol, int D>
 __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     single_pass_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
@@ -341,10 +444,130 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     const int tid_tw = threadIdx.x;
     const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
     for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int tid = opaque_lane();
+        const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
         const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
         single_tile<Sh, Pol, D>(lds, tw, tid, tid_tw, in + seg * Sh::M, out + seg * Sh::M,
                                 seg < batch);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Real-input segments of even length N = 2M through one M-point complex
+// transform.
+// Forward: the N real samples are read as M complex values
+// z[m] = x[2m] + i x[2m+1]; Z = DFT_M(z); with A = Z[k] and
+// B = conj Z[(M-k) mod M], the half spectrum is
+//     X[k] = (A + B)/2 - i W_N^k (A - B)/2,   0 <= k <= M,
+// stored as M+1 complex values per segment.  Z[k] and Z[M-k] sit in
+// different threads, so the last stage writes Z to LDS and the twist
+// reads it back.
+// Inverse (bins 0..M in; bins 0 and M of a real signal are real, their
+// imaginary parts are dropped): with A = X[k] and B = conj X[M-k],
+//     Z[k] = (A + B) + i W_N^{-k} (A - B),   0 <= k < M,
+// and the unnormalised inverse M-point DFT of Z is x[2m] + i x[2m+1]:
+// the N real outputs, written as M complex values.
+// hw holds W_N^k = exp(-2 pi i k / N) for k = 0..M.
+
+// the tile's last stage writes its natural-order outputs to LDS
+template <class Base>
+struct LdsStorePolicy : Base {
+    struct Ctx {
+        c32 *lds;
+        bool valid;
+    };
+    template <class St, int D>
+    static __device__ __forceinline__ void store(const c32 *v, int t, int c, const Ctx &ctx)
+    {
+        if (!ctx.valid)
+            return;
+#pragma unroll
+        for (int u = 0; u < St::U; ++u) {
+            const int b = t + u * Base::kThreads / Base::S;
+            if (St::kFull || b < St::NB) {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    ctx.lds[Base::lds(c, b + r * St::NB)] = v[u * St::R + r];
+            }
+        }
+    }
+};
+
+template <class Sh, class Pol>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    real_forward_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                        const c32 *__restrict__ hw, uint64_t batch)
+{
+    constexpr int M = Sh::M;
+    __shared__ c32 lds[Pol::S * Pol::kSegStride];
+    using LP = LdsStorePolicy<Pol>;
+    using S0 = Stage<Sh, 0, 1>;
+    const int tid_tw = threadIdx.x;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+        const int c = Pol::template col<0>(tid);
+        const int t = Pol::template thr<0>(tid);
+        const uint64_t seg = g * Pol::S + c;
+        const bool valid = seg < batch && Pol::active(tid);
+        c32 v[Sh::kMaxE];
+        const c32 *x = in + seg * M;
+        if (valid)
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        const typename LP::Ctx ctx{lds, valid};
+        if constexpr (Pol::kClassic)
+            tile_run_plain<Sh, LP, -1, 0, 1>(v, lds, tw, tid, ctx);
+        else
+            tile_run<Sh, LP, -1, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+        __syncthreads();
+        if (valid) {
+            c32 *y = out + seg * (uint64_t)(M + 1);
+            for (int k = t; k <= M; k += Sh::T) {
+                const c32 a = lds[Pol::lds(c, k == M ? 0 : k)];
+                const c32 z = lds[Pol::lds(c, k == 0 ? 0 : M - k)];
+                const c32 e = {0.5f * (a.x + z.x), 0.5f * (a.y - z.y)};
+                const c32 d = {0.5f * (a.x - z.x), 0.5f * (a.y + z.y)};  // (A - B) / 2
+                gstore<Pol::kNT>(y + k, cadd(e, cmul(mul_di<-1>(d), hw[k])));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class Sh, class Pol>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    real_inverse_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                        const c32 *__restrict__ hw, uint64_t batch)
+{
+    constexpr int M = Sh::M;
+    __shared__ c32 lds[Pol::kLdsElems];
+    using S0 = Stage<Sh, 0, 1>;
+    const int tid_tw = threadIdx.x;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+        const int t = Pol::template thr<0>(tid);
+        const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+        const typename Pol::Ctx ctx{out + seg * M, seg < batch && Pol::active(tid)};
+        c32 v[Sh::kMaxE];
+        // bins k and M-k of one segment are read by different lanes: plain
+        // loads keep the lines cached for the second read
+        const c32 *x = in + seg * (uint64_t)(M + 1);
+        if (ctx.valid)
+            st_gather<S0, Sh>(v, t, [&](int i) {
+                c32 a = x[i];
+                const c32 z = x[M - i];
+                c32 b = {z.x, -z.y};
+                if (i == 0) {
+                    a.y = 0.f;
+                    b.y = 0.f;
+                }
+                const c32 d = cmulc(csub(a, b), hw[i]);  // (A - B) W_N^{-k}
+                return cadd(cadd(a, b), mul_di<1>(d));
+            });
+        if constexpr (Pol::kClassic)
+            tile_run_plain<Sh, Pol, 1, 0, 1>(v, lds, tw, tid, ctx);
+        else
+            tile_run<Sh, Pol, 1, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
     }
 }
 
@@ -389,10 +612,12 @@ struct FourStepCtx {
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
+    static constexpr bool kPlainLds = false;
+    static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
     static constexpr bool kNT = NT_;
     static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kXcd = Xcd_;
@@ -473,7 +698,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
             continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh, opaque_lane(), threadIdx.x,
+        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
+                                Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
                                 in + seg * nseg, ybuf + seg * nseg, first, n2);
     }
 }
@@ -482,10 +708,12 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
     static constexpr int PS = PS_;
+    static constexpr bool kPlainLds = false;
+    static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
     static constexpr bool kNT = NT_;
     static constexpr int kHoistMask = HoistMask_;
     static constexpr bool kXcd = Xcd_;
@@ -565,7 +793,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
             continue;
         const uint64_t seg = g / blocks;
         const int first = (int)(g - seg * blocks) * Pol::C;
-        row_tile<Sh, Pol, D>(lds, tw, opaque_lane(), threadIdx.x, ybuf + seg * nseg,
+        row_tile<Sh, Pol, D>(lds, tw, Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(),
+                             threadIdx.x, ybuf + seg * nseg,
                              out + seg * nseg, first, n1);
     }
 }

@@ -314,6 +314,8 @@ extern "C" int fft_exec_segments_graph(fft_plan_t plan, const void *in, void *ou
         Plan *p = reinterpret_cast<Plan *>(plan);
         if (!p)
             return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+        if (reject_real(p, "fft_exec_segments_graph") != FFT_OK)
+            return last_status();
         const uint64_t bytes = p->batch * p->n * sizeof(c32);
         int st = check_io(in, out, bytes);
         if (st != FFT_OK)

@@ -66,7 +66,7 @@ def test_factorize_matches_lengths():
             assert v in (2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 25, 32)
             p *= v
         assert p == n, (n, r)
-    assert fs.factorize(4096) == [16, 16, 16]
+    assert fs.factorize(4096) in ([16, 16, 16], [8, 8, 8, 8])
     with pytest.raises(fs.FFTError):
         fs.factorize(14)
 
@@ -88,3 +88,22 @@ def test_split_info_and_forced_variants_are_checked():
         fs.Plan(1 << 20, 4, split_variants=(nc, 0))
     with pytest.raises(fs.FFTError):
         fs.Plan(4096, 4, variant=fs.variant_count(4096) + 3)
+
+
+@pytest.mark.parametrize("args,status", [
+    ((7, 4, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),      # odd
+    ((2, 4, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),      # below the smallest real kernel
+    ((2 * 7 * 64, 4, -1), "FFT_ERR_UNSUPPORTED_LENGTH"),
+    ((1024, 0, -1), "FFT_ERR_INVALID_ARG"),
+    ((1024, 4, 3), "FFT_ERR_INVALID_ARG"),
+])
+def test_real_create_rejects_bad_arguments(args, status):
+    with pytest.raises(fs.FFTError) as ei:
+        fs.RealPlan(*args)
+    assert ei.value.name == status
+
+
+def test_null_plan_frames_and_real():
+    L = fs.lib()
+    assert L.fft_exec_frames(None, None, 0, None, 1, 1, None, None) == -1
+    assert fs.last_error()

@@ -1,0 +1,106 @@
+"""Overlapping, windowed segments (fft_exec_frames) against the FP64
+oracle's short-time transform, on every plan kind: one-pass lengths read
+the frames in the kernel, two-pass and fallback lengths gather first."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1407_6915_amd as fs
+import siggen
+
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def hann32(n):
+    j = np.arange(n, dtype=np.float64)
+    return (0.5 - 0.5 * np.cos(2 * np.pi * j / n)).astype(np.float32)
+
+
+def run_frames(n, x, hop, n_frames, window, direction=fs.FORWARD, batch=None):
+    import torch
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+    wd = None if window is None else torch.from_numpy(window).to("cuda")
+    with fs.Plan(n, batch or n_frames, direction) as p:
+        y = p.exec_frames(xd, hop, n_frames, wd)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().reshape(n_frames, n)
+
+
+@pytest.mark.parametrize("n,hop,frames", [
+    (1024, 256, 37),        # 75 % overlap, ragged last tile
+    (4096, 1024, 21),
+    (4096, 4096, 9),        # disjoint
+    (4096, 4099, 5),        # gaps between frames
+    (1000, 333, 17),        # non power of two, odd hop
+    (16384, 8192, 7),
+    (1 << 16, 1 << 14, 5),  # two-pass length: gathered, then in place
+    (3 ** 9, 5000, 4),      # radix-stage fallback
+    (1, 1, 11),             # identity length
+])
+@pytest.mark.parametrize("windowed", [True, False])
+def test_frames_match_oracle(n, hop, frames, windowed):
+    announce("frames n=%d hop=%d frames=%d window=%s" % (n, hop, frames, windowed))
+    total = (frames - 1) * hop + n + 7          # a few samples past the last frame
+    x = siggen.Signal(seed=41, seg_len=1, sigma=1.0).samples(0, total)
+    w = hann32(n) if windowed else None
+    got = run_frames(n, x, hop, frames, w)
+    ref = oracle.short_time(x, n, hop, frames, w)
+    err = oracle.rel_l2(got, ref)
+    print("  max rel-L2 %.3e" % err.max(), flush=True)
+    assert np.all(err <= oracle.tolerance(n)), err.max()
+
+
+def test_frames_inverse_and_smaller_than_plan():
+    n, hop, frames = 2048, 512, 13
+    announce("frames inverse n=%d" % n)
+    x = siggen.Signal(seed=42, seg_len=1, sigma=1.0).samples(0, (frames - 1) * hop + n)
+    w = np.random.default_rng(3).uniform(0.0, 1.0, n).astype(np.float32)
+    got = run_frames(n, x, hop, frames, w, fs.INVERSE, batch=64)
+    ref = oracle.short_time(x, n, hop, frames, w, fs.INVERSE)
+    assert np.all(oracle.rel_l2(got, ref) <= oracle.tolerance(n))
+
+
+def test_frames_hop_n_equals_segments():
+    """hop == n without a window is the plain disjoint transform: both
+    within the bar of the oracle's records (the two run different kernel
+    instances, so their roundings may differ)."""
+    n, b = 4096, 24
+    announce("frames hop=n vs exec")
+    import torch
+    x = siggen.Signal(seed=43, seg_len=n, sigma=1.0).samples(0, n * b)
+    xd = torch.from_numpy(x).to("cuda")
+    with fs.Plan(n, b) as p:
+        a = p.exec(xd).cpu().numpy().reshape(b, n)
+        f = p.exec_frames(xd, n).cpu().numpy().reshape(b, n)
+    ref = oracle.fft_recursive(x, n)
+    assert np.all(oracle.rel_l2(a, ref) <= oracle.tolerance(n))
+    assert np.all(oracle.rel_l2(f, ref) <= oracle.tolerance(n))
+    assert np.all(oracle.rel_l2(f, a) <= 2 * oracle.tolerance(n))
+
+
+def test_frames_argument_errors():
+    import torch
+    n = 1024
+    announce("frames argument errors")
+    x = torch.zeros(n * 8, dtype=torch.complex64, device="cuda")
+    out = torch.empty(n * 8, dtype=torch.complex64, device="cuda")
+    with fs.Plan(n, 8) as p:
+        cases = [
+            (lambda: p.exec_frames_ptr(x.data_ptr(), x.numel(), out.data_ptr(), 8, 1024 + 1),
+             "FFT_ERR_BOUNDS"),
+            (lambda: p.exec_frames_ptr(x.data_ptr(), x.numel(), out.data_ptr(), 9, 512),
+             "FFT_ERR_INVALID_ARG"),
+            (lambda: p.exec_frames_ptr(x.data_ptr(), x.numel(), out.data_ptr(), 2, 0),
+             "FFT_ERR_INVALID_ARG"),
+            (lambda: p.exec_frames_ptr(x.data_ptr(), x.numel(), x.data_ptr() + 8 * 64, 2, 64),
+             "FFT_ERR_OVERLAP"),
+            (lambda: p.exec_frames_ptr(x.data_ptr() + 4, n * 2, out.data_ptr(), 2, 64),
+             "FFT_ERR_ALIGNMENT"),
+        ]
+        for f, name in cases:
+            with pytest.raises(fs.FFTError) as e:
+                f()
+            assert e.value.name == name
+    torch.cuda.synchronize()

@@ -235,7 +235,8 @@ def test_exec_rejects_memory_it_cannot_use():
 def test_plan_describe():
     announce("describe")
     d = fs.Plan(4096, 8).describe()
-    assert d["kind"] == "single_pass" and d["radices"] == [16, 16, 16]
+    assert d["kind"] == "single_pass" and d["radices"] == fs.factorize(4096)
+    assert int(np.prod(d["radices"])) == 4096
     d = fs.Plan(1 << 20, 2).describe()
     assert d["kind"] == "four_step" and d["n1"] * d["n2"] == 1 << 20
     d = fs.Plan(3 ** 9, 2).describe()
