@@ -28,15 +28,18 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "single_pass_n4096_traffic.json")
 
 
+# the sources that define and instantiate the one-pass kernels
+KERNEL_SOURCES = ("radix.hpp", "tile.hpp", "registry.hpp", "kernels_single.hip")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the device sources: measured HBM traffic is only reported
-    while it was taken on the kernels as they are now."""
+    """Hash of the one-pass kernels' device sources: measured HBM traffic is
+    only reported while it was taken on the kernels as they are now."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1407_6915_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

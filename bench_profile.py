@@ -5,7 +5,7 @@ under profiles/.
   kernels  <kernel_stats.csv> <out.md> <command...>
            per-kernel call count and average/min/max duration
   traffic  <fetch counter_collection.csv> <write counter_collection.csv>
-           <out.json> <samples per launch>
+           <out.json> <samples per launch> [<fetch command> <write command>]
            HBM bytes per launch of the transform kernel, from FETCH_SIZE and
            WRITE_SIZE (KiB per dispatch), each scaled by what the same counter
            reads for the plain device copy of a known size in the same run
@@ -53,10 +53,14 @@ def _per_kernel(counter_csv: str, counter: str):
     return out
 
 
+def _is_fft(name: str) -> bool:
+    return "single_pass_kernel" in name or "single_pass_plain_kernel" in name
+
+
 def _split(per_kernel):
-    fft = {k: v for k, v in per_kernel.items() if "single_pass_kernel" in k}
+    fft = {k: v for k, v in per_kernel.items() if _is_fft(k)}
     copy = {k: v for k, v in per_kernel.items()
-            if "single_pass_kernel" not in k and ("copy" in k.lower() or "elementwise" in k.lower())}
+            if not _is_fft(k) and ("copy" in k.lower() or "elementwise" in k.lower())}
     if len(fft) != 1 or not copy:
         raise SystemExit("expected one transform kernel and a copy kernel, got %s"
                          % sorted(per_kernel))
@@ -65,7 +69,8 @@ def _split(per_kernel):
     return fk, fv, ck, copy[ck]
 
 
-def traffic(fetch_csv: str, write_csv: str, out_json: str, samples: int) -> None:
+def traffic(fetch_csv: str, write_csv: str, out_json: str, samples: int,
+            commands=()) -> None:
     known = samples * 8.0                      # bytes the copy reads, and writes
     f_name, f_fft, c_name, f_copy = _split(_per_kernel(fetch_csv, "FETCH_SIZE"))
     _, w_fft, _, w_copy = _split(_per_kernel(write_csv, "WRITE_SIZE"))
@@ -86,6 +91,7 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, samples: int) -> None
         "hbm_bytes_per_launch": fetch + write,
         "traffic_over_algorithmic": (fetch + write) / (16.0 * samples),
         "kernel_source_hash": bench.kernel_source_hash(),
+        "commands": list(commands),
     }
     json.dump(out, open(out_json, "w"), indent=1)
     print(json.dumps(out))
@@ -95,6 +101,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         kernels(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6:8])
     else:
         raise SystemExit(__doc__)

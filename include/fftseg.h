@@ -226,9 +226,9 @@ int fft_exec_file(fft_plan_t plan, const char *in_path, uint64_t in_offset,
                   fft_stream_stats_t *stats);
 
 /* ------------------------------------------------------------------------
- * Uneven batches: one persistent launch over a work list (Sec. III batches
+ * Uneven batches: a persistent kernel over a work list (Sec. III batches
  * the segments of a block into one plan; here segments of several lengths,
- * at any offsets, share one kernel launch).
+ * at any offsets, share one kernel).
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -246,8 +246,8 @@ int fft_worklist_supported(uint32_t segment_len);
 
 /* Compile n entries into workgroup tasks: segments are grouped by length,
  * packed S per tile for short lengths, split into column/row tiles for the
- * two-pass lengths; the task list, per-length twiddle tables, counters and
- * the two-pass scratch are uploaded once.  Output ranges must not overlap
+ * two-pass lengths; the task list, per-length twiddle tables and the
+ * two-pass scratch (one Y buffer per two-pass segment) are uploaded once.  Output ranges must not overlap
  * (FFT_ERR_OVERLAP); an unsupported length gives FFT_ERR_UNSUPPORTED_LENGTH.
  * n may be 0 (an empty list to fill later with fft_worklist_reset).  All
  * entry checks run before any device work.  NULL on error. */
@@ -261,8 +261,11 @@ fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direct
  * list is re-filled with whatever segments are ready. */
 int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, void *stream);
 
-/* Run every entry: one counter-clearing kernel and one persistent kernel
- * whose workgroups claim tasks through an atomic cursor.  in_base and
+/* Run every entry: a cursor-clearing kernel, then the persistent kernel
+ * twice (workgroups claim tasks through an atomic cursor): first over the
+ * first-pass tiles of the two-pass segments and the one-pass tiles, then
+ * over the second-pass tiles, which the launch boundary orders after their
+ * first passes.  in_base and
  * out_base are device pointers; every entry's range must lie in its
  * buffer's allocation (FFT_ERR_BOUNDS).  in_base == out_base is allowed
  * when each entry's output range either equals its input range or overlaps
@@ -275,8 +278,9 @@ int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_ba
                             void *stream);
 
 /* Synchronise `stream` and report whether the last run on it completed:
- * FFT_ERR_TIMEOUT if a second-pass tile gave up waiting for its first pass
- * (its outputs are then not written). */
+ * FFT_ERR_HIP if the stream reports an error or a launch left tasks
+ * unclaimed.  (No work-list kernel waits on another workgroup, so
+ * FFT_ERR_TIMEOUT is not returned here.) */
 int fft_worklist_status(fft_worklist_t wl, void *stream);
 
 /* JSON summary (items, tasks, per-length counts, scratch bytes, grid). */

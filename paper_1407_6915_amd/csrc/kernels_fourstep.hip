@@ -99,21 +99,21 @@ const ColumnDesc kColumns[] = {
     ColInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
     ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     ColInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    ColInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(0),
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
-    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
+    ColInst<256, 16, 16, 4, 0, 16, 16>::desc(4),
     ColInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
     ColInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
     ColInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
     ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
     ColInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(2),
-    ColInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
+    ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(0),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
-    ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
+    ColInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(3),
     ColInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
     ColInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
     ColInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),
@@ -129,21 +129,21 @@ const RowDesc kRows[] = {
     RowInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
     RowInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     RowInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    RowInst<256, 16, 16, 4, 0, 16, 16>::desc(0),
+    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(0),
     RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
-    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(4),
+    RowInst<256, 16, 16, 4, 0, 16, 16>::desc(4),
     RowInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
     RowInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
     RowInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
     RowInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(0),
     RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(1),
     RowInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(2),
-    RowInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(0),
+    RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(0),
     RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(1),
     RowInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(2),
-    RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(3),
+    RowInst<1024, 64, 8, 4, 0, 16, 16, 4>::desc(3),
     RowInst<1024, 64, 4, 4, kXcd, 16, 16, 4>::desc(4),
     RowInst<1024, 64, 8, 4, kNT | kXcd | kHoistLast | kW2, 16, 16, 4>::desc(5),
     RowInst<1024, 64, 8, 4, kNT | kXcd | kNoHoist | kW2, 16, 16, 4>::desc(6),

@@ -143,7 +143,7 @@ const SinglePassDesc kTable[] = {
     SpInst<2048, 128, 2, 4, kNT | kPlain, 16, 16, 8>::desc(1, 64),
     SpInst<2048, 128, 2, 4, kPlain, 16, 16, 8>::desc(2, 32),
     SpInst<2048, 128, 2, 4, kClassic, 16, 16, 8>::desc(3, 32),
-    SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 32),
+    SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 64),
     SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
     SpInst<4096, 512, 1, 4, kNT | kPlain | kAux, 8, 8, 8, 8>::desc(2, 64),
     SpInst<4096, 256, 1, 0, kNT | kPlain, 16, 16, 16>::desc(3, 32),

@@ -343,6 +343,7 @@ unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev
 // workgroup walks tiles with a grid-stride loop, so twiddles loaded once
 // stay in registers); FFTSEG_GRID_MULT=0 gives one workgroup per tile.
 constexpr int kDefaultGridMult = 8;
+constexpr int kTwoPassGridMult = 32;  // measured best for the four-step passes
 
 int env_grid_mult()
 {
@@ -401,7 +402,7 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
     }
     p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / n));
     if (!getenv("FFTSEG_GRID_MULT"))
-        p->grid_mult = tuned_grid_mult(n, -1, p->grid_mult);
+        p->grid_mult = tuned_grid_mult(n, -1, kTwoPassGridMult);
     int cv = 0, rv = 0;
     if (forced_split_variants >= 0) {
         cv = forced_split_variants & 0xff;

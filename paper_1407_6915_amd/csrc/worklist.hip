@@ -1,19 +1,19 @@
-// Uneven batches in one persistent launch (fft_worklist_*).
+// Uneven batches in two persistent launches (fft_worklist_*).
 //
 // The paper batches the fixed-length segments of one block into one plan
 // (Sec. III); here segments of different lengths, at arbitrary offsets, go
-// through ONE kernel launch.  The host compiles the entries into tasks,
+// through one persistent kernel.  The host compiles the entries into tasks,
 // each filling one 256-thread workgroup tile:
 //   single pass  up to S whole segments of one length (S = 16 for 256, ...)
 //   two pass     one column tile (pass A) or row tile (pass B) of a
 //                four-step segment (16384 = 128 x 128, 65536 = 256 x 256)
 // Workgroups claim tasks (a few at a time) through an atomic cursor in list
-// order: all pass-A tasks first, then single-pass tasks (longest first),
-// then pass-B tasks.
-// A pass-B tile waits until its segment's pass-A tiles have signalled a
-// per-segment counter.  Those tiles were claimed earlier by workgroups that
-// are running and never wait, so every wait ends; a bounded spin still
-// caps it and raises an error flag instead of hanging.
+// order.  The kernel runs twice: first over every pass-A task and every
+// single-pass task (longest first), then over every pass-B task.  The
+// kernel boundary orders a segment's second pass after its first, so no
+// workgroup waits on another and no device-scope fence is needed (on this
+// chip such a release/acquire pair writes back or invalidates a whole XCD's
+// L2, which costs far more than the launch).
 #include "fftseg.h"
 #include "runtime.hpp"
 #include "tile.hpp"
@@ -54,9 +54,7 @@ struct Task {
     uint32_t count;   // single pass: segments in the task (whole tiles of S)
     uint32_t tile;    // two pass: first column/row block
     uint32_t ntiles;  // two pass: blocks in the task
-    uint32_t dep;     // two pass: per-segment counter index
-    uint32_t need;    // pass B: first-pass tasks of the segment to wait for
-    uint32_t pad;
+    uint32_t pad[3];
 };
 
 struct Tables {      // per kind, device pointers
@@ -107,9 +105,6 @@ static_assert(PCol128::kThreads == kThreads && PRow128::kThreads == kThreads &&
                   PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
                   PCol1k::kThreads == kThreads && PRow1k::kThreads == kThreads,
               "two-pass routines use the whole workgroup");
-
-// spin bound for a pass-B wait (~tens of ms, far above one tile's time)
-constexpr uint32_t kSpinLimit = 1u << 20;
 
 // tasks claimed per atomic on the cursor
 constexpr uint32_t kClaim = 4;
@@ -164,46 +159,14 @@ __device__ __forceinline__ void run_rows(c32 *lds, const Tables &tb, const Task 
     }
 }
 
-__device__ __forceinline__ void signal_done(uint32_t *counter, int tid)
-{
-    __threadfence();  // release this tile's stores device-wide
-    __syncthreads();
-    if (tid == 0)
-        atomicAdd(counter, 1u);
-}
-
-// wait until *counter >= target; returns false (and raises the error flag)
-// if the bound is hit
-__device__ __forceinline__ bool wait_for(uint32_t *counter, uint32_t target, uint32_t *err,
-                                         int tid, uint32_t *s_ok)
-{
-    if (tid == 0) {
-        uint32_t spins = 0, ok = 1;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(8);
-            if (++spins > kSpinLimit) {
-                atomicOr(err, 1u);
-                ok = 0;
-                break;
-            }
-        }
-        *s_ok = ok;
-    }
-    __syncthreads();
-    const bool ok = *s_ok != 0;
-    __threadfence();  // acquire the producers' stores
-    return ok;
-}
-
 template <int D>
 __global__ void __launch_bounds__(kThreads)
     worklist_kernel(const Task *__restrict__ tasks, uint32_t n_tasks,
                     const Item *__restrict__ items, const Tables *__restrict__ tables,
-                    const c32 *in, c32 *out, c32 *ybuf, uint32_t *ctl)
+                    const c32 *in, c32 *out, c32 *ybuf, uint32_t *cursor)
 {
-    // ctl[0]: task cursor, ctl[1]: error flag, ctl[2..]: per-segment counters
     __shared__ c32 lds[kLdsElems];
-    __shared__ uint32_t s_task, s_ok;
+    __shared__ uint32_t s_task;
     for (;;) {
         // lane index made opaque per task: keeps the compiler from lifting
         // every routine's lane-derived addresses out of the loop (they
@@ -211,16 +174,13 @@ __global__ void __launch_bounds__(kThreads)
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         if (tid == 0)
-            s_task = atomicAdd(&ctl[0], kClaim);
+            s_task = atomicAdd(cursor, kClaim);
         __syncthreads();
         const uint32_t base = s_task;
         __syncthreads();
         if (base >= n_tasks)
             break;
         const uint32_t end = base + kClaim < n_tasks ? base + kClaim : n_tasks;
-        // claimed tasks run in list order: first-pass tasks precede every
-        // second-pass task in the list, so a wait below never depends on a
-        // task this workgroup still holds
         for (uint32_t ti = base; ti < end; ++ti) {
             tid = opaque(tid);
             const Task t = tasks[ti];
@@ -234,27 +194,21 @@ __global__ void __launch_bounds__(kThreads)
             case K6000: run_single<Sh6000, P6000, D>(lds, tb, t, items, in, out, tid); break;
             case K16384A:
                 run_columns<Sh128, PCol128, D>(lds, tb, t, items, in, ybuf, tid, 128);
-                signal_done(&ctl[2 + t.dep], tid);
                 break;
             case K65536A:
                 run_columns<Sh256c, PCol256, D>(lds, tb, t, items, in, ybuf, tid, 256);
-                signal_done(&ctl[2 + t.dep], tid);
                 break;
             case K1MA:
                 run_columns<Sh1k, PCol1k, D>(lds, tb, t, items, in, ybuf, tid, 1024);
-                signal_done(&ctl[2 + t.dep], tid);
                 break;
             case K16384B:
-                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
-                    run_rows<Sh128, PRow128, D>(lds, tb, t, items, ybuf, out, tid, 128);
+                run_rows<Sh128, PRow128, D>(lds, tb, t, items, ybuf, out, tid, 128);
                 break;
             case K65536B:
-                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
-                    run_rows<Sh256c, PRow256, D>(lds, tb, t, items, ybuf, out, tid, 256);
+                run_rows<Sh256c, PRow256, D>(lds, tb, t, items, ybuf, out, tid, 256);
                 break;
             case K1MB:
-                if (wait_for(&ctl[2 + t.dep], t.need, &ctl[1], tid, &s_ok))
-                    run_rows<Sh1k, PRow1k, D>(lds, tb, t, items, ybuf, out, tid, 1024);
+                run_rows<Sh1k, PRow1k, D>(lds, tb, t, items, ybuf, out, tid, 1024);
                 break;
             default: break;
             }
@@ -263,8 +217,8 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-// zero the cursor, the error flag and the counters (a kernel rather than a
-// memset so the whole launch sequence can be captured into a graph)
+// zero the two launches' cursors (a kernel rather than a memset so the whole
+// launch sequence can be captured into a graph)
 __global__ void __launch_bounds__(256) clear_kernel(uint32_t *ctl, uint32_t n)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -316,7 +270,8 @@ struct WorkList {
     uint64_t n_items = 0;
     uint64_t max_in = 0, max_out = 0;  // highest sample touched (+1)
     bool in_place_ok = false;          // outputs hit no other entry's input
-    uint32_t n_tasks = 0, n_dep = 0;
+    uint32_t n_tasks = 0, n_first = 0;  // tasks; of which run in the first launch
+    uint32_t n_two_pass = 0;            // two-pass segments
     uint64_t counts[wl::KCOUNT] = {};
     uint64_t samples = 0;
     size_t y_bytes = 0;
@@ -509,31 +464,30 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
                 in_place_ok = false;
         }
     }
-    // tasks: all pass-A tiles, then single-pass tiles, then pass-B tiles;
-    // longest lengths first within each group
+    // tasks: all pass-A tiles, then single-pass tiles (first launch), then
+    // pass-B tiles (second launch); longest lengths first within each group
     tasks.clear();
     hitems.clear();
     hitems.reserve(n);
     std::vector<Task> a_tasks, s_tasks, b_tasks;
     uint64_t y_samples = 0;
-    uint32_t dep = 0;
+    uint32_t two_pass = 0;
     uint64_t counts[KCOUNT] = {};
     for (int li = (int)NL - 1; li >= 0; --li) {
         const LengthInfo &L = kLengths[li];
         const auto &b = bucket[li];
         if (L.two_pass) {
-            const uint32_t per_seg = (uint32_t)((L.per_tile + L.group - 1) / L.group);
             for (uint32_t idx : b) {
                 const uint32_t item = (uint32_t)hitems.size();
                 hitems.push_back({items[idx].in_off, items[idx].out_off, y_samples});
                 y_samples += L.n;
                 for (int t = 0; t < L.per_tile; t += L.group) {
                     const uint32_t nt = (uint32_t)std::min(L.group, L.per_tile - t);
-                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, nt, dep, 0, 0});
-                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, nt, dep, per_seg, 0});
+                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, nt, {0, 0, 0}});
+                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, nt, {0, 0, 0}});
                 }
                 counts[L.a] += 1;
-                ++dep;
+                ++two_pass;
             }
         } else {
             const size_t per_task = (size_t)L.per_tile * (size_t)L.group;
@@ -542,7 +496,7 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
                 const uint32_t cnt = (uint32_t)std::min<size_t>(per_task, b.size() - k);
                 for (uint32_t j = 0; j < cnt; ++j)
                     hitems.push_back({items[b[k + j]].in_off, items[b[k + j]].out_off, 0});
-                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, 0, 0, 0});
+                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, {0, 0, 0}});
                 counts[L.a] += cnt;
             }
         }
@@ -559,7 +513,8 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     w->samples = samples;
     w->in_place_ok = in_place_ok;
     w->n_tasks = (uint32_t)tasks.size();
-    w->n_dep = dep;
+    w->n_first = (uint32_t)(a_tasks.size() + s_tasks.size());
+    w->n_two_pass = two_pass;
     w->y_bytes = y_samples * sizeof(c32);
     std::memcpy(w->counts, counts, sizeof(counts));
     return FFT_OK;
@@ -596,7 +551,7 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
     int st = wl_compile(w, items, n, tasks, hitems);
     if (st != FFT_OK)
         return st;
-    const size_t need_ctl = 2 + (size_t)w->n_dep;
+    const size_t need_ctl = 2;  // one task cursor per launch
     const size_t need_y = w->y_bytes / sizeof(c32);
     if (tasks.size() > w->cap_tasks || hitems.size() > w->cap_items || need_ctl > w->cap_ctl ||
         need_y > w->cap_y) {
@@ -606,7 +561,7 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
                 FFT_OK ||
             (st = grow(&w->d_items, &w->cap_items, std::max<size_t>(hitems.size(), 1), "items")) !=
                 FFT_OK ||
-            (st = grow(&w->d_ctl, &w->cap_ctl, need_ctl, "counters")) != FFT_OK ||
+            (st = grow(&w->d_ctl, &w->cap_ctl, need_ctl, "cursors")) != FFT_OK ||
             (st = grow(&w->d_y, &w->cap_y, std::max<size_t>(need_y, 1), "two-pass scratch")) !=
                 FFT_OK)
             return st;
@@ -655,17 +610,23 @@ int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
     using namespace wl;
     if (w->n_tasks == 0)
         return set_ok();
-    const uint32_t nctl = 2 + w->n_dep;
-    hipLaunchKernelGGL(clear_kernel, dim3(std::min<uint32_t>((nctl + 255) / 256, 1024)),
-                       dim3(256), 0, s, w->d_ctl, nctl);
-    if (w->dir < 0)
-        hipLaunchKernelGGL((worklist_kernel<-1>), dim3(w->grid), dim3(kThreads), 0, s,
-                           w->d_tasks, w->n_tasks, w->d_items, w->d_tables, (const c32 *)in,
-                           (c32 *)out, w->d_y, w->d_ctl);
-    else
-        hipLaunchKernelGGL((worklist_kernel<1>), dim3(w->grid), dim3(kThreads), 0, s,
-                           w->d_tasks, w->n_tasks, w->d_items, w->d_tables, (const c32 *)in,
-                           (c32 *)out, w->d_y, w->d_ctl);
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, w->d_ctl, 2u);
+    // launch 0: pass-A and single-pass tasks; launch 1: pass-B tasks
+    const uint32_t first[2] = {0, w->n_first};
+    const uint32_t count[2] = {w->n_first, w->n_tasks - w->n_first};
+    for (int l = 0; l < 2; ++l) {
+        if (count[l] == 0)
+            continue;
+        const unsigned grid = std::min<unsigned>(w->grid, (count[l] + kClaim - 1) / kClaim);
+        if (w->dir < 0)
+            hipLaunchKernelGGL((worklist_kernel<-1>), dim3(grid), dim3(kThreads), 0, s,
+                               w->d_tasks + first[l], count[l], w->d_items, w->d_tables,
+                               (const c32 *)in, (c32 *)out, w->d_y, w->d_ctl + l);
+        else
+            hipLaunchKernelGGL((worklist_kernel<1>), dim3(grid), dim3(kThreads), 0, s,
+                               w->d_tasks + first[l], count[l], w->d_items, w->d_tables,
+                               (const c32 *)in, (c32 *)out, w->d_y, w->d_ctl + l);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return hip_error(e, "work-list launch");
@@ -821,13 +782,15 @@ extern "C" int fft_worklist_status(fft_worklist_t wlh, void *stream)
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess)
         return hip_error(e, "hipStreamSynchronize");
+    // both launches drain their task lists; every task was claimed iff the
+    // cursors passed the list ends
     if (!w->d_ctl || w->n_tasks == 0)
         return set_ok();
-    uint32_t flag = 0;
-    if ((e = hipMemcpy(&flag, w->d_ctl + 1, sizeof(flag), hipMemcpyDeviceToHost)) != hipSuccess)
+    uint32_t cur[2] = {0, 0};
+    if ((e = hipMemcpy(cur, w->d_ctl, sizeof(cur), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_error(e, "status read");
-    if (flag)
-        return set_error(FFT_ERR_TIMEOUT, "a two-pass tile gave up waiting for its first pass");
+    if (cur[0] < w->n_first || cur[1] < w->n_tasks - w->n_first)
+        return set_error(FFT_ERR_HIP, "the last run did not claim every task");
     return set_ok();
 }
 
@@ -838,7 +801,8 @@ extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
         return set_error(FFT_ERR_INVALID_ARG, "work list is NULL");
     std::string js = "{\"items\":" + std::to_string(w->n_items) +
                      ",\"tasks\":" + std::to_string(w->n_tasks) +
-                     ",\"two_pass_segments\":" + std::to_string(w->n_dep) +
+                     ",\"first_launch_tasks\":" + std::to_string(w->n_first) +
+                     ",\"two_pass_segments\":" + std::to_string(w->n_two_pass) +
                      ",\"samples\":" + std::to_string(w->samples) +
                      ",\"scratch_bytes\":" + std::to_string(w->y_bytes) +
                      ",\"in_place_ok\":" + (w->in_place_ok ? "true" : "false") +
