@@ -88,7 +88,7 @@ def bench_large(args):
     torch.cuda.set_device(dev)
     xd = torch.from_numpy(x_host.reshape(-1)).to(dev)
     yd = torch.empty_like(xd)
-    plan = fs.Plan(n, b, fs.FORWARD)
+    plan = fs.Plan(n, b, fs.FORWARD, args.variant)
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--batch", type=int, default=262144)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="force a compiled kernel variant of the 4096-point plan "
+                         "(default: the planner's choice)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="also time a plain device copy of the same size")
     ap.add_argument("--workload", default="large",

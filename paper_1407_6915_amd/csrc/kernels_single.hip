@@ -151,6 +151,9 @@ const SinglePassDesc kTable[] = {
     SpInst<4096, 256, 1, 4, kPlain, 16, 16, 16>::desc(5, 32),
     SpInst<4096, 256, 1, 0, kClassic | kNT, 16, 16, 16>::desc(6, 32),
     SpInst<4096, 512, 1, 4, kClassic | kNT, 8, 8, 8, 8>::desc(7, 32),
+    shuffle4096_desc(8, 64, 2),
+    shuffle4096_desc(9, 64, 0),
+    shuffle4096_desc(10, 32, 2),
     SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(0, 32),
     SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(1, 32),
     SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(2, 32),

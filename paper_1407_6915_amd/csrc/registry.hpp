@@ -33,6 +33,7 @@ struct SinglePassDesc {
     int hoist;          // bit i: stage i keeps its twiddles in registers across segments
     int grid_mult;      // default persistent grid: resident waves of workgroups
     int lds_bytes;
+    int shuffle;        // 1: an exchange between stages runs through lane shuffles
     int nrad;
     int radices[kMaxRadices];
     sp_launch_fn launch;
@@ -60,6 +61,8 @@ struct RowDesc {
 };
 
 const SinglePassDesc *single_pass_table(int *count);
+// the 4096-point pass with a lane-shuffle exchange (kernels_shuffle.hip)
+SinglePassDesc shuffle4096_desc(int variant, int grid_mult, int nontemporal);
 const ColumnDesc *column_table(int *count);
 const RowDesc *row_table(int *count);
 

@@ -642,11 +642,12 @@ int plan_describe(const Plan *p, std::string &js)
                  "{\"kind\":\"single_pass\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
                  "\"variant\":%d,\"radices\":%s,\"threads_per_segment\":%d,"
                  "\"segments_per_workgroup\":%d,\"lds_pad_shift\":%d,\"nontemporal\":%d,"
-                 "\"lds_bytes\":%d,\"grid_mult\":%d,\"scratch_bytes\":0}",
+                 "\"lds_bytes\":%d,\"shuffle_exchange\":%d,\"grid_mult\":%d,"
+                 "\"scratch_bytes\":0}",
                  (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
                  p->sp->variant, rad(p->sp->radices, p->sp->nrad).c_str(), p->sp->threads,
                  p->sp->segs_per_wg, p->sp->pad_shift, p->sp->nontemporal,
-                 p->sp->lds_bytes, p->grid_mult);
+                 p->sp->lds_bytes, p->sp->shuffle, p->grid_mult);
         break;
     case Plan::FOURSTEP:
         snprintf(buf, sizeof buf,
