@@ -55,6 +55,16 @@ def measured_traffic(samples: int):
     return t.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_host, n: int, budget_s: float):
     """The FP64 oracle (recursive radix-2/3/5, OpenMP over segments) on a
     seeded prefix of the same input, sized to about budget_s seconds."""
@@ -69,7 +79,7 @@ def cpu_baseline(x_host, n: int, budget_s: float):
     dt = time.perf_counter() - t0
     flops = 5.0 * n * math.log2(n) * m
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": oracle.max_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": "first %d of the workload's segments (%.1f s, FP64 recursive "
                       "radix-2/3/5 DFT)" % (m, dt)}
 
@@ -109,6 +119,7 @@ def bench_large(args):
     wall = time.perf_counter() - t0
     kernel_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    med_kernel_s = sorted(kernel_ms)[len(kernel_ms) // 2] / 1e3
     ms_per_step = wall / args.steps * 1e3
 
     flops = 5.0 * n * math.log2(n) * b
@@ -141,6 +152,7 @@ def bench_large(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel_avg_us": round(avg_kernel_s * 1e6, 2),
+                     "kernel_median_us": round(med_kernel_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if args.copy_reference:

@@ -17,9 +17,12 @@ namespace {
 // segments of the persistent loop / LDS addresses are computed per access;
 // kClassic = the plainly written kernel (see SinglePassPolicy); kAux = this
 // row also provides the length's frame (overlapping segment) and
-// real-input kernels (one row per length).
+// real-input kernels (one row per length); kPrefetch = the plainly written
+// kernel with the next segment's loads issued ahead (implies the classic
+// policy).
 constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
-              kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256;
+              kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256,
+              kPrefetch = 512;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -37,13 +40,15 @@ struct SpInst {
     using Sh = Shape<N, T, Radices<Rs...>>;
     using Pol = SinglePassPolicy<Sh, S, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                                  false, waves<F>(), (F & kPlainLane) != 0,
-                                 (F & kPlainLds) != 0, (F & kClassic) != 0>;
+                                 (F & kPlainLds) != 0, (F & (kClassic | kPrefetch)) != 0>;
 
     using kernel_fn = void (*)(const c32 *, c32 *, const c32 *, uint64_t);
     template <int D>
     static constexpr kernel_fn kernel()
     {
-        if constexpr ((F & kClassic) != 0)
+        if constexpr ((F & kPrefetch) != 0)
+            return &single_pass_prefetch_kernel<Sh, Pol, D>;
+        else if constexpr ((F & kClassic) != 0)
             return &single_pass_plain_kernel<Sh, Pol, D>;
         else
             return &single_pass_kernel<Sh, Pol, D>;
@@ -154,14 +159,17 @@ const SinglePassDesc kTable[] = {
     shuffle4096_desc(8, 64, 2),
     shuffle4096_desc(9, 64, 0),
     shuffle4096_desc(10, 32, 2),
-    SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(0, 32),
-    SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(1, 32),
-    SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(2, 32),
-    SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(3, 32),
+    SpInst<4096, 256, 1, 0, kPrefetch | kNT, 16, 16, 16>::desc(11, 32),
+    SpInst<4096, 512, 1, 4, kPrefetch | kNT, 8, 8, 8, 8>::desc(12, 32),
+    SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(0, 32),
+    SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(1, 32),
+    SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(2, 32),
+    SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(3, 32),
+    SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(4, 32),
+    SpInst<8192, 512, 1, 4, kPrefetch | kNT, 16, 16, 16, 2>::desc(5, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(0, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(1, 32),
     SpInst<16384, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),
-    SpInst<16384, 1024, 1, 4, kClassic | kNT, 16, 16, 16, 4>::desc(3, 32),
     // mixed radix 2/3/5
     SpInst<1000, 100, 2, 4, kClassic, 10, 10, 10>::desc(0, 64),
     SpInst<1000, 100, 2, 4, kPlain, 10, 10, 10>::desc(1, 64),
@@ -175,6 +183,7 @@ const SinglePassDesc kTable[] = {
     SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(1, 0),
     SpInst<6000, 300, 1, 4, kNT | kNoHoist | kAux, 20, 20, 15>::desc(2, 32),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist | kPlain, 16, 15, 25>::desc(3, 32),
+    SpInst<6000, 400, 1, 4, kPrefetch | kNT, 16, 15, 25>::desc(4, 32),
 };
 
 }  // namespace

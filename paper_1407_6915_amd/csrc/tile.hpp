@@ -435,6 +435,46 @@ __global__ void __launch_bounds__(Pol::kThreads)
     }
 }
 
+// single_pass_plain_kernel with the next segment's stage-0 loads issued
+// before the current segment's stages (software pipelining in registers):
+// for lengths whose LDS footprint leaves few workgroups per CU, the loads of
+// segment g + grid are in flight while segment g is transformed and stored.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads)
+    single_pass_prefetch_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                                uint64_t batch)
+{
+    __shared__ c32 lds[Pol::kLdsElems];
+    using S0 = Stage<Sh, 0, 1>;
+    const int tid = threadIdx.x;
+    const int slot = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    c32 nx[Sh::kMaxE];
+    uint64_t g = blockIdx.x;
+    {
+        const uint64_t seg = g * Pol::S + slot;
+        if (g < groups && seg < batch) {
+            const c32 *x = in + seg * Sh::M;
+            st_gather<S0, Sh>(nx, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        }
+    }
+    for (; g < groups; g += gridDim.x) {
+        const uint64_t seg = g * Pol::S + slot;
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch};
+        c32 v[Sh::kMaxE];
+#pragma unroll
+        for (int i = 0; i < Sh::kMaxE; ++i)
+            v[i] = nx[i];
+        const uint64_t gn = g + gridDim.x, segn = gn * Pol::S + slot;
+        if (gn < groups && segn < batch) {
+            const c32 *x = in + segn * Sh::M;
+            st_gather<S0, Sh>(nx, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        }
+        tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
 template <class Sh, class Pol, int D>
 __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     single_pass_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
