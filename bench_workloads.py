@@ -216,7 +216,7 @@ def serving(args):
     budget_bytes = 200 * 10 ** 9
     max_launch = 1 << 31                                   # bounds the two-pass scratch
     arena_samples = (budget_bytes - max_launch * 8) // 8
-    ex = GpuExecutor(arena_samples)
+    ex = GpuExecutor(arena_samples, max_launch_samples=max_launch)
     # saturation: the same jobs, every one queued at t = 0, through each path
     sat_f = job_states(1e9, min(args.jobs, 300), 99)
     sat_c = [JobState(j.index, j.arrival_s, j.seg_len, j.n_seg, j.host_in, j.host_out)

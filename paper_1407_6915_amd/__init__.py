@@ -433,6 +433,13 @@ class WorkList:
     @staticmethod
     def _items(entries):
         import numpy as np
+        work_dtype = np.dtype([("in_off", "<u8"), ("out_off", "<u8"),
+                               ("segment_len", "<u4"), ("job", "<u4")])
+        if (isinstance(entries, np.ndarray) and entries.dtype == work_dtype
+                and entries.ndim == 1 and entries.flags["C_CONTIGUOUS"] and len(entries)):
+            # same layout as fft_work_t: hand the array over without a copy
+            # (the caller's array must stay alive for the call)
+            return entries.ctypes.data_as(ctypes.POINTER(WorkItem)), len(entries)
         if isinstance(entries, np.ndarray) and entries.dtype.names:
             arr = np.ascontiguousarray(entries)
             n = len(arr)
@@ -485,7 +492,7 @@ class WorkList:
         return out
 
     def status(self, stream=None) -> None:
-        """Synchronise and raise FFTError if a second-pass wait gave up."""
+        """Synchronise and raise FFTError if the last run did not complete."""
         _check(lib().fft_worklist_status(self.handle, _stream_handle(stream)))
 
     def describe(self) -> dict:

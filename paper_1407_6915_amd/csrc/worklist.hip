@@ -413,13 +413,35 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
         bucket[li - kLengths].push_back((uint32_t)i);
         samples += len;
     }
+    // The range checks work on runs: maximal stretches of consecutive
+    // entries of one length whose inputs and outputs both advance by that
+    // length (a job's segments, typically).  Entries of one run never
+    // overlap each other, so checking the runs' extents is the same as
+    // checking every entry, at a cost set by the number of runs.
+    struct Run {
+        uint64_t in0, in1, out0, out1;  // input and output extents [0, 1)
+        bool same;                      // in0 == out0: the run is in place
+    };
+    std::vector<Run> runs;
+    for (size_t i = 0; i < n; ++i) {
+        const uint64_t len = items[i].segment_len;
+        const uint64_t ia = items[i].in_off, oa = items[i].out_off;
+        if (i > 0 && items[i - 1].segment_len == len && ia == runs.back().in1 &&
+            oa == runs.back().out1) {
+            runs.back().in1 += len;
+            runs.back().out1 += len;
+        } else {
+            runs.push_back({ia, ia + len, oa, oa + len, ia == oa});
+        }
+    }
+    const size_t nr = runs.size();
     // outputs must not overlap each other
     {
-        std::vector<std::pair<uint64_t, uint64_t>> r(n);
-        for (size_t i = 0; i < n; ++i)
-            r[i] = {items[i].out_off, items[i].out_off + items[i].segment_len};
+        std::vector<std::pair<uint64_t, uint64_t>> r(nr);
+        for (size_t i = 0; i < nr; ++i)
+            r[i] = {runs[i].out0, runs[i].out1};
         std::sort(r.begin(), r.end());
-        for (size_t i = 1; i < n; ++i)
+        for (size_t i = 1; i < nr; ++i)
             if (r[i].first < r[i - 1].second)
                 return set_error(FFT_ERR_OVERLAP, "two work items write overlapping outputs");
     }
@@ -427,20 +449,20 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     // input: inputs sorted by start, prefix top-2 of their ends; an output
     // [a, b) meets input j iff start_j < b and end_j > a
     bool in_place_ok = true;
-    if (n) {
-        std::vector<size_t> ord(n);
-        for (size_t i = 0; i < n; ++i)
+    if (nr) {
+        std::vector<size_t> ord(nr);
+        for (size_t i = 0; i < nr; ++i)
             ord[i] = i;
         std::sort(ord.begin(), ord.end(),
-                  [&](size_t x, size_t y) { return items[x].in_off < items[y].in_off; });
-        std::vector<uint64_t> starts(n);
-        for (size_t k = 0; k < n; ++k)
-            starts[k] = items[ord[k]].in_off;
-        std::vector<std::pair<uint64_t, size_t>> best(n), second(n);
+                  [&](size_t x, size_t y) { return runs[x].in0 < runs[y].in0; });
+        std::vector<uint64_t> starts(nr);
+        for (size_t k = 0; k < nr; ++k)
+            starts[k] = runs[ord[k]].in0;
+        std::vector<std::pair<uint64_t, size_t>> best(nr), second(nr);
         std::pair<uint64_t, size_t> b1{0, SIZE_MAX}, b2{0, SIZE_MAX};
-        for (size_t k = 0; k < n; ++k) {
+        for (size_t k = 0; k < nr; ++k) {
             const size_t j = ord[k];
-            const std::pair<uint64_t, size_t> e{items[j].in_off + items[j].segment_len, j};
+            const std::pair<uint64_t, size_t> e{runs[j].in1, j};
             if (e.first > b1.first) {
                 b2 = b1;
                 b1 = e;
@@ -450,14 +472,14 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
             best[k] = b1;
             second[k] = b2;
         }
-        for (size_t i = 0; i < n && in_place_ok; ++i) {
-            const uint64_t a = items[i].out_off, b = a + items[i].segment_len;
+        for (size_t i = 0; i < nr && in_place_ok; ++i) {
+            const uint64_t a = runs[i].out0, b = runs[i].out1;
             const size_t k =
                 (size_t)(std::lower_bound(starts.begin(), starts.end(), b) - starts.begin());
             if (k == 0)
                 continue;
             const auto &m1 = best[k - 1], &m2 = second[k - 1];
-            const bool own_same = items[i].in_off == a;
+            const bool own_same = runs[i].same;
             if (m1.first > a && !(m1.second == i && own_same))
                 in_place_ok = false;
             else if (m1.second == i && own_same && m2.first > a)

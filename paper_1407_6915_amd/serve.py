@@ -145,7 +145,8 @@ class GpuExecutor:
     three torch streams (copy in, transform, copy out), one reusable work
     list re-filled for every packed launch."""
 
-    def __init__(self, arena_samples: int, direction: int = FORWARD, device: str = "cuda"):
+    def __init__(self, arena_samples: int, direction: int = FORWARD, device: str = "cuda",
+                 max_launch_samples: int = 0):
         import torch
         from . import WorkList
         self.torch = torch
@@ -156,10 +157,32 @@ class GpuExecutor:
         self.s_comp = torch.cuda.Stream(self.dev)
         self.s_out = torch.cuda.Stream(self.dev)
         self.wl = WorkList((), direction)
+        if max_launch_samples:
+            self.reserve(max_launch_samples)
         self.t0 = time.perf_counter()
         self.launches: List[List[int]] = []
         self.max_launch_samples = 0
         self._comp_ev = None
+
+    def reserve(self, max_launch_samples: int) -> None:
+        """Grow the work list's device arrays to what a launch of up to
+        max_launch_samples can need (task and item lists of the shortest
+        length, two-pass scratch of the longest), so that no later reset
+        has to synchronise the device and reallocate while jobs are in
+        flight.  Only the capacities are kept."""
+        import numpy as np
+        from . import worklist_supported
+        lens = [n for n in (256, 1000, 1024, 1536, 4096, 6000, 16384, 65536, 1 << 20)
+                if worklist_supported(n)]
+        for n in (min(lens), max(lens)):
+            cnt = max(1, max_launch_samples // n)
+            ent = np.zeros(cnt, dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                                       ("segment_len", "<u4"), ("job", "<u4")])
+            ent["in_off"] = ent["out_off"] = np.arange(cnt, dtype=np.uint64) * np.uint64(n)
+            ent["segment_len"] = n
+            self.wl.reset(ent, stream=self.s_comp.cuda_stream)
+        self.wl.reset((), stream=self.s_comp.cuda_stream)
+        self.torch.cuda.synchronize(self.dev)
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -249,10 +272,17 @@ class RejectedJob(Exception):
 
 
 def serve(jobs: List[JobState], executor, arena_samples: int,
-          max_launch_samples: int = 1 << 31, reject_oversized: bool = True) -> dict:
+          max_launch_samples: int = 1 << 31, reject_oversized: bool = True,
+          max_copies_in_flight: int = 8) -> dict:
     """Run every job through the continuous-batching loop.  Jobs must be
     sorted by arrival time.  Returns latency and throughput statistics;
-    per-job timestamps are written into the JobState objects."""
+    per-job timestamps are written into the JobState objects.
+
+    At most ``max_copies_in_flight`` host-to-device copies are queued at a
+    time: a deep copy queue can block the host thread inside the runtime,
+    and while it is blocked no transform or device-to-host copy is issued,
+    so the two directions of the host link would run one after the other
+    instead of together."""
     arena = Arena(arena_samples)
     n = len(jobs)
     nxt = 0
@@ -273,7 +303,7 @@ def serve(jobs: List[JobState], executor, arena_samples: int,
             nxt += 1
         progressed = False
         # admission: arrival order, while the head of the queue fits
-        while pending:
+        while pending and len(copying) < max_copies_in_flight:
             head = pending[0]
             if not arena.fits_ever(head.samples) or head.samples > max_launch_samples:
                 pending.popleft()

@@ -107,3 +107,33 @@ def test_null_plan_frames_and_real():
     L = fs.lib()
     assert L.fft_exec_frames(None, None, 0, None, 1, 1, None, None) == -1
     assert fs.last_error()
+
+
+def _work(entries):
+    import numpy as np
+    ent = np.zeros(len(entries), dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                                        ("segment_len", "<u4"), ("job", "<u4")])
+    for i, (a, b, n) in enumerate(entries):
+        ent[i] = (a, b, n, 0)
+    return ent
+
+
+@pytest.mark.parametrize("entries,ok", [
+    # a job's run of segments, then another run
+    ([(0, 0, 1024), (1024, 1024, 1024), (1024, 1024, 1024)], False),   # repeated output
+    ([(0, 0, 1024), (1024, 1024, 1024), (4096, 4096, 4096)], True),
+    ([(0, 0, 4096), (4096, 4096, 4096), (6000, 7000, 1024)], False),    # inside run 1's output
+    ([(0, 8192, 4096), (4096, 12288, 4096), (0, 16384, 256)], True),    # inputs may overlap
+    ([(0, 100, 256), (256, 356, 256), (512, 0, 256)], False),           # [0,256) vs [100,..)
+])
+def test_worklist_output_overlap_checked_on_runs(entries, ok):
+    """Entries are grouped into runs for the range checks; overlaps between
+    outputs of different runs, or inside what looks like a run, are found
+    before any device work (a valid list then fails only for the missing
+    device)."""
+    with pytest.raises(fs.FFTError) as e:
+        fs.WorkList(_work(entries))
+    if ok:
+        assert e.value.name in ("FFT_ERR_HIP", "FFT_ERR_OUT_OF_MEMORY"), e.value
+    else:
+        assert e.value.name == "FFT_ERR_OVERLAP", e.value

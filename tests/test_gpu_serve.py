@@ -66,6 +66,22 @@ def test_alone_equals_mix_and_matches_oracle():
     assert bitwise == len(jobs)
 
 
+def test_reserved_capacity_then_serving():
+    announce("serving: reserved work-list capacity")
+    jobs, keep = make_jobs(8, seed_offset=11)
+    arena = sum(j.samples for j in jobs) + 64 * len(jobs)
+    ex = GpuExecutor(arena, max_launch_samples=1 << 22)
+    st = serve(jobs, ex, arena, max_launch_samples=1 << 22)
+    assert st["completed"] + st["rejected"] == len(jobs)
+    for j in jobs:
+        if j.status != "done":
+            continue
+        x = keep[2 * j.index].numpy().reshape(j.n_seg, j.seg_len)
+        y = keep[2 * j.index + 1].numpy().reshape(j.n_seg, j.seg_len)
+        ref = oracle.fft_recursive(x[0], j.seg_len)
+        assert oracle.rel_l2(y[0][None], ref)[0] <= oracle.tolerance(j.seg_len)
+
+
 def test_budget_smaller_than_the_mix():
     announce("serving: tight budget")
     jobs, keep = make_jobs(12, seed_offset=9)
