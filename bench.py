@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per rate")
     ap.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.0,1.2,1.5,2.0",
                     help="serving: arrival rates as fractions of the plain path's saturation")
+    ap.add_argument("--inflight", type=int, default=8,
+                    help="serving: host-to-device copies the scheduler keeps in flight")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path shards by contiguous segment "

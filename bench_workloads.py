@@ -224,7 +224,8 @@ def serving(args):
     st_sat = serve_fifo(sat_f, plans, fifo_arena)
     lam_sat = st_sat["jobs_per_s"]
     ex.t0 = time.perf_counter()
-    st_sat_c = serve(sat_c, ex, arena_samples, max_launch_samples=max_launch)
+    st_sat_c = serve(sat_c, ex, arena_samples, max_launch_samples=max_launch,
+                     max_copies_in_flight=args.inflight)
     rows = []
     for k, frac in enumerate(float(r) for r in args.rates.split(",")):
         lam = frac * lam_sat
@@ -233,7 +234,8 @@ def serving(args):
                   for j in jobs_c]
         ex.t0 = time.perf_counter()
         ex.launches.clear()
-        sc = serve(jobs_c, ex, arena_samples, max_launch_samples=max_launch)
+        sc = serve(jobs_c, ex, arena_samples, max_launch_samples=max_launch,
+                   max_copies_in_flight=args.inflight)
         sf = serve_fifo(jobs_f, plans, fifo_arena)
         rows.append({"rate_frac": frac, "rate_jobs_per_s": round(lam, 2),
                      "continuous": {key: round(sc[key], 3) for key in
@@ -246,6 +248,7 @@ def serving(args):
     for p in plans.values():
         p.close()
     print(json.dumps({"workload": "serving", "jobs_per_rate": args.jobs,
+                      "copies_in_flight": args.inflight,
                       "plain_saturation_jobs_per_s": round(lam_sat, 2),
                       "continuous_saturation_jobs_per_s": round(st_sat_c["jobs_per_s"], 2),
                       "saturation_payload_GBps": {
