@@ -136,9 +136,10 @@ const SinglePassDesc kTable[] = {
     SpInst<256, 16, 8, 4, kNT | kPlain, 16, 16>::desc(1, 32),
     SpInst<256, 16, 8, 4, kNT, 16, 16>::desc(2, 32),
     SpInst<256, 16, 8, 4, kClassic | kNT, 16, 16>::desc(3, 64),
-    SpInst<512, 64, 4, 4, kNT | kPlain | kAux, 8, 8, 8>::desc(0, 0),
+    SpInst<512, 64, 4, 4, kNT | kPlain, 8, 8, 8>::desc(0, 0),
     SpInst<512, 64, 4, 4, kPlain, 8, 8, 8>::desc(1, 32),
     SpInst<512, 32, 8, 4, kNT | kPlain, 16, 16, 2>::desc(2, 64),
+    SpInst<512, 64, 4, 4, kClassic | kNT | kAux, 8, 8, 8>::desc(3, 32),
     SpInst<1024, 64, 2, 4, kNT | kPlain | kAux, 16, 16, 4>::desc(0, 64),
     SpInst<1024, 64, 4, 4, kNT | kPlain, 16, 16, 4>::desc(1, 64),
     SpInst<1024, 64, 4, 4, kPlain, 16, 16, 4>::desc(2, 32),
