@@ -1,0 +1,69 @@
+// Single-pass and four-step pass instances with split LDS exchanges (real
+// parts, then imaginary parts): half the LDS of the complex tile, so lengths
+// whose tile otherwise leaves one or two workgroups per CU get twice as
+// many.  The 1024-point radix-32 x 32 four-step tiles measured beside them
+// live here too.  Kept in a translation unit of their own so they do not
+// share inlined code with the other instances.
+#include "fsinst.hpp"
+#include "spinst.hpp"
+
+namespace fftseg {
+
+SinglePassDesc split_desc(int config, int variant, int grid_mult)
+{
+    using namespace sp;
+    //                       N      T   S  PS  F                             radices
+    switch (config) {
+    case 0:
+        return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 16, 32, 32>::desc(
+            variant, grid_mult);
+    case 1:
+        return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 32, 32, 16>::desc(
+            variant, grid_mult);
+    case 2:
+        return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 16, 16, 16, 4>::desc(
+            variant, grid_mult);
+    case 3:
+        return SpInst<16384, 512, 1, 4, kSplit | kPrefetch | kNT | kNoHoist | kW2, 32, 32,
+                      16>::desc(variant, grid_mult);
+    default:
+        return SinglePassDesc{};
+    }
+}
+
+ColumnDesc split_column_desc(int config, int variant)
+{
+    using namespace fs;
+    //                        M     T   C  PS  F                                  radices
+    switch (config) {
+    case 0:
+        return ColInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 16, 16, 4>::desc(variant);
+    case 1:
+        return ColInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
+    case 2:
+        return ColInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
+    case 3:
+        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+    default:
+        return ColumnDesc{};
+    }
+}
+
+RowDesc split_row_desc(int config, int variant)
+{
+    using namespace fs;
+    switch (config) {
+    case 0:
+        return RowInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 16, 16, 4>::desc(variant);
+    case 1:
+        return RowInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
+    case 2:
+        return RowInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
+    case 3:
+        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+    default:
+        return RowDesc{};
+    }
+}
+
+}  // namespace fftseg

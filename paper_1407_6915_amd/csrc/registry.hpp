@@ -63,6 +63,11 @@ struct RowDesc {
 const SinglePassDesc *single_pass_table(int *count);
 // the 4096-point pass with a lane-shuffle exchange (kernels_shuffle.hip)
 SinglePassDesc shuffle4096_desc(int variant, int grid_mult, int nontemporal);
+// single-pass and four-step instances with split LDS exchanges
+// (kernels_split.hip)
+SinglePassDesc split_desc(int config, int variant, int grid_mult);
+ColumnDesc split_column_desc(int config, int variant);
+RowDesc split_row_desc(int config, int variant);
 const ColumnDesc *column_table(int *count);
 const RowDesc *row_table(int *count);
 

@@ -274,6 +274,116 @@ __device__ __forceinline__ void tile_run_plain(c32 *v, c32 *lds, const c32 *__re
     }
 }
 
+// One half (F = 0: real parts, F = 1: imaginary parts) of an LDS exchange
+// through a float array indexed like the complex one (see lds_scatter and
+// lds_gather).
+template <int F>
+__device__ __forceinline__ float &part(c32 &a)
+{
+    if constexpr (F == 0)
+        return a.x;
+    else
+        return a.y;
+}
+template <int F>
+__device__ __forceinline__ float part(const c32 &a)
+{
+    if constexpr (F == 0)
+        return a.x;
+    else
+        return a.y;
+}
+
+template <class St, class Sh, class Pol, int L, int F>
+__device__ __forceinline__ void lds_scatter_part(const c32 *v, int t, int c, float *lds)
+{
+    using Run = LdsRun<Pol, L, St::R>;
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            const int base = (b / L) * (L * St::R) + (b % L);
+            if constexpr (Run::kSep) {
+                float *p = lds + Pol::lds(c, base);
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    p[r * Run::kStride] = part<F>(v[u * St::R + r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    lds[Pol::lds(c, base + r * L)] = part<F>(v[u * St::R + r]);
+            }
+        }
+    }
+}
+
+template <class St, class Sh, class Pol, int F>
+__device__ __forceinline__ void lds_gather_part(c32 *v, int t, int c, const float *lds)
+{
+    using Run = LdsRun<Pol, St::NB, St::R>;
+#pragma unroll
+    for (int u = 0; u < St::U; ++u) {
+        const int b = t + u * Sh::T;
+        if (St::kFull || b < St::NB) {
+            if constexpr (Run::kStrided && !Pol::kPlainLds) {
+                const float *p = lds + Pol::lds(c, b);
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    part<F>(v[u * St::R + r]) = p[r * Run::kStride];
+            } else {
+#pragma unroll
+                for (int r = 0; r < St::R; ++r)
+                    part<F>(v[u * St::R + r]) = lds[Pol::lds(c, b + r * St::NB)];
+            }
+        }
+    }
+}
+
+// tile_run with every LDS exchange split in two: the real parts go through
+// LDS first, then the imaginary parts, through a float array with the same
+// (padded) indexing as the complex one.  The tile then needs half the LDS,
+// so twice as many workgroups fit a CU, for two more barriers per exchange.
+// Between the halves a register slot holds the next stage's real part and
+// this stage's imaginary part.
+template <class Sh, class Pol, int D, int I, int L>
+__device__ __forceinline__ void tile_run_split(c32 *v, float *lds, const c32 *__restrict__ tw,
+                                               int tid, int tid_tw,
+                                               const typename Pol::Ctx &ctx)
+{
+    using St = Stage<Sh, I, L>;
+    const int c = Pol::template col<I>(tid);
+    const int t = Pol::template thr<I>(tid);
+    const bool act = Pol::active(tid);
+    if (act)
+        st_compute<St, Sh, L, D, Pol::hoists(I)>(v, Pol::template thr<I>(tid_tw), tw);
+    if constexpr (St::kLast) {
+        if (act)
+            Pol::template store<St, D>(v, t, c, ctx);
+    } else {
+        using Nx = Stage<Sh, I + 1, L * St::R>;
+        const int c2 = Pol::template col<I + 1>(tid);
+        const int t2 = Pol::template thr<I + 1>(tid);
+        if (act)
+            lds_scatter_part<St, Sh, Pol, L, 0>(v, t, c, lds);
+        __syncthreads();
+        if (act)
+            lds_gather_part<Nx, Sh, Pol, 0>(v, t2, c2, lds);
+        __syncthreads();
+        if (act)
+            lds_scatter_part<St, Sh, Pol, L, 1>(v, t, c, lds);
+        __syncthreads();
+        if (act)
+            lds_gather_part<Nx, Sh, Pol, 1>(v, t2, c2, lds);
+        __syncthreads();
+        tile_run_split<Sh, Pol, D, I + 1, L * St::R>(v, lds, tw, tid, tid_tw, ctx);
+    }
+}
+
+// LDS of a tile in complex elements: Elems complex values, or Elems floats
+// (rounded up) when the exchanges are split
+template <int Elems, bool Split>
+constexpr int lds_c32() { return Split ? (Elems + 1) / 2 : Elems; }
+
 // a copy of the lane index the compiler cannot treat as loop-invariant
 __device__ __forceinline__ int opaque_lane()
 {
@@ -292,7 +402,7 @@ __device__ __forceinline__ int opaque_lane()
 // the waves per SIMD the register allocation must allow.)
 template <class Sh, int S_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Partial_ = false, int Waves_ = 1, bool PlainLane_ = false,
-          bool PlainLds_ = false, bool Classic_ = false>
+          bool PlainLds_ = false, bool Classic_ = false, bool Split_ = false>
 struct SinglePassPolicy {
     static constexpr int S = S_;
     static constexpr int PS = PS_;
@@ -300,8 +410,10 @@ struct SinglePassPolicy {
     // compiler derives from it) across segments instead of recomputing it;
     // PlainLds: every LDS access computes its padded address on its own;
     // Classic: the stages run through tile_run_plain (both of the above,
-    // and no per-stage choices left to the policy)
+    // and no per-stage choices left to the policy); Split: the exchanges
+    // run through tile_run_split (real and imaginary halves)
     static constexpr bool kPlainLane = PlainLane_ || Classic_;
+    static constexpr bool kSplit = Split_;
     static constexpr bool kPlainLds = PlainLds_;
     static constexpr bool kClassic = Classic_;
     static constexpr bool kNT = NT_;
@@ -472,6 +584,70 @@ __global__ void __launch_bounds__(Pol::kThreads)
             st_gather<S0, Sh>(nx, t, [&](int i) { return gload<Pol::kNT>(x + i); });
         }
         tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
+// single_pass_kernel with split exchanges (tile_run_split): for lengths
+// whose complex LDS tile leaves one or two workgroups per CU.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    single_pass_split_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                             uint64_t batch)
+{
+    static_assert(Pol::kSplit, "split exchanges only");
+    __shared__ float lds[Pol::kLdsElems];
+    const int tid_tw = threadIdx.x;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+        const int t = Pol::template thr<0>(tid);
+        const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch && Pol::active(tid)};
+        const c32 *x = in + seg * Sh::M;
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        if (ctx.valid)
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        tile_run_split<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+    }
+}
+
+// single_pass_split_kernel with the next segment's stage-0 loads issued
+// before the current segment's stages, as in single_pass_prefetch_kernel.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    single_pass_split_prefetch_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                                      uint64_t batch)
+{
+    static_assert(Pol::kSplit, "split exchanges only");
+    __shared__ float lds[Pol::kLdsElems];
+    using S0 = Stage<Sh, 0, 1>;
+    const int tid = threadIdx.x;
+    const int slot = Pol::template col<0>(tid);
+    const int t = Pol::template thr<0>(tid);
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    c32 nx[Sh::kMaxE];
+    uint64_t g = blockIdx.x;
+    {
+        const uint64_t seg = g * Pol::S + slot;
+        if (g < groups && seg < batch) {
+            const c32 *x = in + seg * Sh::M;
+            st_gather<S0, Sh>(nx, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        }
+    }
+    for (; g < groups; g += gridDim.x) {
+        const uint64_t seg = g * Pol::S + slot;
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch && Pol::active(tid)};
+        c32 v[Sh::kMaxE];
+#pragma unroll
+        for (int i = 0; i < Sh::kMaxE; ++i)
+            v[i] = nx[i];
+        const uint64_t gn = g + gridDim.x, segn = gn * Pol::S + slot;
+        if (gn < groups && segn < batch) {
+            const c32 *x = in + segn * Sh::M;
+            st_gather<S0, Sh>(nx, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        }
+        tile_run_split<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid, ctx);
     }
 }
 
@@ -655,9 +831,10 @@ struct FourStepCtx {
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
+    static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
     static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
@@ -722,7 +899,11 @@ __device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw
     using S0 = Stage<Sh, 0, 1>;
     const c32 *xc = x + first + c;
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+    if constexpr (Pol::kSplit)
+        tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
+                                         ctx);
+    else
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 template <class Sh, class Pol, int D>
@@ -731,7 +912,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
                              const c32 *__restrict__ tl, const c32 *__restrict__ th,
                              int sh, int n2, uint64_t batch)
 {
-    __shared__ c32 lds[Pol::kLdsElems];
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
@@ -751,9 +932,10 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
+    static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
     static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
@@ -818,7 +1000,11 @@ __device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, i
     using S0 = Stage<Sh, 0, 1>;
     const c32 *yr = y + (size_t)(first + c) * Sh::M;
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+    if constexpr (Pol::kSplit)
+        tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
+                                         ctx);
+    else
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 template <class Sh, class Pol, int D>
@@ -826,7 +1012,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     four_step_rows_kernel(const c32 *ybuf, c32 *out, const c32 *__restrict__ tw,
                           int n1, uint64_t batch)
 {
-    __shared__ c32 lds[Pol::kLdsElems];
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n1;
     const uint64_t blocks = (uint64_t)(n1 / Pol::C);
     const uint64_t tiles = batch * blocks;

@@ -70,6 +70,40 @@ def test_every_variant(n):
             check(n, run(n, x, d, variant=v), x, d, what="variant %d dir %d" % (v, d))
 
 
+@pytest.mark.parametrize("n", [4096, 8192, 16384])
+def test_every_variant_walks_several_segments(n, monkeypatch):
+    """A persistent grid of one resident wave of workgroups, so every
+    workgroup transforms several segments in turn and reuses its LDS (the
+    batches above fit one segment per workgroup at these lengths)."""
+    monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
+    b = (1 << 24) // n + 5
+    x = noise(n, b, seed=n + 3)
+    ref = {d: oracle.fft_recursive(x, n, d) for d in (fs.FORWARD, fs.INVERSE)}
+    for v in range(fs.variant_count(n)):
+        announce("n=%d variant=%d batch=%d grid_mult=1" % (n, v, b))
+        for d in (fs.FORWARD, fs.INVERSE):
+            e = oracle.rel_l2(run(n, x, d, variant=v), ref[d])
+            assert np.all(e <= oracle.tolerance(n)), (v, d, float(e.max()))
+
+
+def test_four_step_tiles_walk_several_tiles(monkeypatch):
+    """The same for the column and row passes of the 2^20-point split."""
+    import torch
+    monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
+    n, b = 1 << 20, 9
+    n1, n2, nc, nr = fs.split_info(n)
+    x = noise(n, b, seed=29)
+    ref = {d: oracle.fft_recursive(x, n, d) for d in (fs.FORWARD, fs.INVERSE)}
+    xd = torch.from_numpy(x.reshape(-1)).cuda()
+    for c, r in [(0, 0)] + [(v, v) for v in range(1, min(nc, nr))]:
+        announce("n=%d column variant %d row variant %d batch=%d grid_mult=1" % (n, c, r, b))
+        for d in (fs.FORWARD, fs.INVERSE):
+            with fs.Plan(n, b, d, split_variants=(c, r)) as p:
+                y = p.exec(xd).cpu().numpy().reshape(b, n)
+            e = oracle.rel_l2(y, ref[d])
+            assert np.all(e <= oracle.tolerance(n)), (c, r, d, float(e.max()))
+
+
 @pytest.mark.parametrize("n", [1 << 15, 1 << 16, 1 << 18, 1 << 20, 1 << 22])
 def test_every_four_step_tile_variant(n):
     n1, n2, nc, nr = fs.split_info(n)
