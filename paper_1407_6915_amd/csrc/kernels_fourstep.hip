@@ -21,12 +21,12 @@ const ColumnDesc kColumns[] = {
     ColInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
     ColInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
     ColInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
-    split_column_desc(4, 0),
+    radix32_column_desc(1, 0),
     ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(1),
     ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(2),
     ColInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(3),
-    split_column_desc(5, 4),
-    split_column_desc(3, 0),
+    radix32_column_desc(2, 4),
+    radix32_column_desc(0, 0),
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
     ColInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(3),
@@ -57,12 +57,12 @@ const RowDesc kRows[] = {
     RowInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
     RowInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
     RowInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
-    split_row_desc(4, 0),
+    radix32_row_desc(1, 0),
     RowInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(1),
     RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(2),
     RowInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(3),
-    split_row_desc(5, 4),
-    split_row_desc(3, 0),
+    radix32_row_desc(2, 4),
+    radix32_row_desc(0, 0),
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
     RowInst<1024, 64, 8, 4, kNT | kXcd, 16, 16, 4>::desc(3),

@@ -1,0 +1,42 @@
+// Four-step tiles with radix-32 stages: 1024 = 32 x 32 and 512 = 32 x 16
+// take two Stockham stages, so one LDS exchange (two barriers) per tile
+// instead of two or three, for 32 values per thread.  (The same radices in
+// one-pass kernels of 512 and 1024 points measured no faster than the
+// table's defaults.)  Kept in a translation unit of their own so they do not
+// share inlined code with the other instances.
+#include "fsinst.hpp"
+
+namespace fftseg {
+
+ColumnDesc radix32_column_desc(int config, int variant)
+{
+    using namespace fs;
+    //                        M     T   C  PS  F                        radices
+    switch (config) {
+    case 0:
+        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+    case 1:
+        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
+    case 2:
+        return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
+    default:
+        return ColumnDesc{};
+    }
+}
+
+RowDesc radix32_row_desc(int config, int variant)
+{
+    using namespace fs;
+    switch (config) {
+    case 0:
+        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+    case 1:
+        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
+    case 2:
+        return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
+    default:
+        return RowDesc{};
+    }
+}
+
+}  // namespace fftseg

@@ -1,9 +1,8 @@
 // Single-pass and four-step pass instances with split LDS exchanges (real
 // parts, then imaginary parts): half the LDS of the complex tile, so lengths
 // whose tile otherwise leaves one or two workgroups per CU get twice as
-// many.  The radix-32 four-step tiles measured beside them live here too.
-// Kept in a translation unit of their own so they do not share inlined code
-// with the other instances.
+// many.  Kept in a translation unit of their own so they do not share
+// inlined code with the other instances.
 #include "fsinst.hpp"
 #include "spinst.hpp"
 
@@ -42,12 +41,6 @@ ColumnDesc split_column_desc(int config, int variant)
         return ColInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
     case 2:
         return ColInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
-    case 3:
-        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
-    case 4:
-        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
-    case 5:
-        return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     default:
         return ColumnDesc{};
     }
@@ -63,12 +56,6 @@ RowDesc split_row_desc(int config, int variant)
         return RowInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
     case 2:
         return RowInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
-    case 3:
-        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
-    case 4:
-        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
-    case 5:
-        return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     default:
         return RowDesc{};
     }

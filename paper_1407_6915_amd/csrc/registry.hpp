@@ -68,6 +68,9 @@ SinglePassDesc shuffle4096_desc(int variant, int grid_mult, int nontemporal);
 SinglePassDesc split_desc(int config, int variant, int grid_mult);
 ColumnDesc split_column_desc(int config, int variant);
 RowDesc split_row_desc(int config, int variant);
+// four-step tiles with radix-32 stages (kernels_radix32.hip)
+ColumnDesc radix32_column_desc(int config, int variant);
+RowDesc radix32_row_desc(int config, int variant);
 const ColumnDesc *column_table(int *count);
 const RowDesc *row_table(int *count);
 
