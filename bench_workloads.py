@@ -98,7 +98,7 @@ def uneven(args):
         p.close()
     flops = float(sum(FLOP(int(n)) for n in lengths))
     comp = 16.0 * total
-    plan_bytes = float(sum(16 * n * (2 if n in (16384, 65536) else 1) for n in lengths))
+    plan_bytes = float(sum(16 * n * (2 if n == 65536 else 1) for n in lengths))
     out = {"workload": workloads.UNEVEN["name"], "segments": len(lengths), "samples": total,
            "worklist": desc, "build_s": round(t_build, 3),
            "persistent_ms": round(t_wl * 1e3, 3), "persistent_graph_ms": round(t_graph * 1e3, 3),

@@ -241,13 +241,15 @@ typedef struct {
 typedef struct fftseg_worklist *fft_worklist_t;
 
 /* 1 if segment_len has a work-list routine (256, 1000, 1024, 1536, 4096,
- * 6000 in one pass; 16384, 65536 and 2^20 in two passes), else 0. */
+ * 6000 and 16384 in one pass; 65536 and 2^20 in two passes), else 0. */
 int fft_worklist_supported(uint32_t segment_len);
 
 /* Compile n entries into workgroup tasks: segments are grouped by length,
  * packed S per tile for short lengths, split into column/row tiles for the
- * two-pass lengths; the task list, per-length twiddle tables and the
- * two-pass scratch (one Y buffer per two-pass segment) are uploaded once.  Output ranges must not overlap
+ * two-pass lengths; 16384-point segments become "wide" tiles of their own
+ * launch (one 512-thread workgroup per segment).  The task list,
+ * per-length twiddle tables and the two-pass scratch (one Y buffer per
+ * two-pass segment) are uploaded once.  Output ranges must not overlap
  * (FFT_ERR_OVERLAP); an unsupported length gives FFT_ERR_UNSUPPORTED_LENGTH.
  * n may be 0 (an empty list to fill later with fft_worklist_reset).  All
  * entry checks run before any device work.  NULL on error. */
@@ -265,7 +267,8 @@ int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, voi
  * twice (workgroups claim tasks through an atomic cursor): first over the
  * first-pass tiles of the two-pass segments and the one-pass tiles, then
  * over the second-pass tiles, which the launch boundary orders after their
- * first passes.  in_base and
+ * first passes.  The wide tiles run between the two, as a persistent
+ * grid-stride launch over the 16384-point segments.  in_base and
  * out_base are device pointers; every entry's range must lie in its
  * buffer's allocation (FFT_ERR_BOUNDS).  in_base == out_base is allowed
  * when each entry's output range either equals its input range or overlaps
@@ -283,7 +286,8 @@ int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_ba
  * FFT_ERR_TIMEOUT is not returned here.) */
 int fft_worklist_status(fft_worklist_t wl, void *stream);
 
-/* JSON summary (items, tasks, per-length counts, scratch bytes, grid). */
+/* JSON summary (items, tasks, wide segments, per-length counts, scratch
+ * bytes, grids). */
 int fft_worklist_describe(fft_worklist_t wl, char *buf, size_t len);
 
 /* Synchronise the device, then free the work list.  NULL is a no-op. */

@@ -6,7 +6,7 @@
 // each filling one 256-thread workgroup tile:
 //   single pass  up to S whole segments of one length (S = 16 for 256, ...)
 //   two pass     one column tile (pass A) or row tile (pass B) of a
-//                four-step segment (16384 = 128 x 128, 65536 = 256 x 256)
+//                four-step segment (65536 = 256 x 256, 2^20 = 1024 x 1024)
 // Workgroups claim tasks (a few at a time) through an atomic cursor in list
 // order.  The kernel runs twice: first over every pass-A task and every
 // single-pass task (longest first), then over every pass-B task.  The
@@ -14,6 +14,10 @@
 // workgroup waits on another and no device-scope fence is needed (on this
 // chip such a release/acquire pair writes back or invalidates a whole XCD's
 // L2, which costs far more than the launch).
+// 16384-point segments are "wide": their one-pass tile (512 threads, split
+// LDS exchanges) does not fit the 256-thread workgroup, so they run in a
+// launch of their own between the two, one segment per workgroup tile,
+// instead of as two passes of 128 x 128.
 #include "fftseg.h"
 #include "runtime.hpp"
 #include "tile.hpp"
@@ -33,8 +37,7 @@ enum Kind : uint32_t {
     K1536,
     K4096,
     K6000,
-    K16384A,
-    K16384B,
+    K16384W,
     K65536A,
     K65536B,
     K1MA,
@@ -79,9 +82,6 @@ using Sh4096 = Shape<4096, 256, Radices<16, 16, 16>>;
 using P4096 = SinglePassPolicy<Sh4096, 1, 4, true, 0, false>;
 using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
 using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false>;
-using Sh128 = Shape<128, 8, Radices<16, 8>>;
-using PCol128 = ColumnPolicy<Sh128, 32, 4, true, 0>;
-using PRow128 = RowPolicy<Sh128, 32, 4, true, 0>;
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
 using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0>;
 using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0>;
@@ -93,21 +93,21 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLdsElems =
     cmax(cmax(cmax(P256::kLdsElems, P1000::kLdsElems), cmax(P1024::kLdsElems, P1536::kLdsElems)),
          cmax(cmax(P4096::kLdsElems, P6000::kLdsElems),
-              cmax(cmax(cmax(PCol128::kLdsElems, PRow128::kLdsElems),
-                        cmax(PCol256::kLdsElems, PRow256::kLdsElems)),
+              cmax(cmax(PCol256::kLdsElems, PRow256::kLdsElems),
                    cmax(PCol1k::kLdsElems, PRow1k::kLdsElems))));
 
 static_assert(P256::kThreads <= kThreads && P1000::kThreads <= kThreads &&
                   P1024::kThreads <= kThreads && P1536::kThreads <= kThreads &&
                   P4096::kThreads <= kThreads && P6000::kThreads <= kThreads,
               "single-pass routines must fit the workgroup");
-static_assert(PCol128::kThreads == kThreads && PRow128::kThreads == kThreads &&
-                  PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
+static_assert(PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
                   PCol1k::kThreads == kThreads && PRow1k::kThreads == kThreads,
               "two-pass routines use the whole workgroup");
 
 // tasks claimed per atomic on the cursor
 constexpr uint32_t kClaim = 4;
+// persistent grid of the wide launch: resident workgroup waves per CU
+constexpr int kWideGridMult = 32;
 
 // a value the compiler must recompute per loop iteration (see below)
 __device__ __forceinline__ int opaque(int v)
@@ -192,17 +192,11 @@ __global__ void __launch_bounds__(kThreads)
             case K1536: run_single<Sh1536, P1536, D>(lds, tb, t, items, in, out, tid); break;
             case K4096: run_single<Sh4096, P4096, D>(lds, tb, t, items, in, out, tid); break;
             case K6000: run_single<Sh6000, P6000, D>(lds, tb, t, items, in, out, tid); break;
-            case K16384A:
-                run_columns<Sh128, PCol128, D>(lds, tb, t, items, in, ybuf, tid, 128);
-                break;
             case K65536A:
                 run_columns<Sh256c, PCol256, D>(lds, tb, t, items, in, ybuf, tid, 256);
                 break;
             case K1MA:
                 run_columns<Sh1k, PCol1k, D>(lds, tb, t, items, in, ybuf, tid, 1024);
-                break;
-            case K16384B:
-                run_rows<Sh128, PRow128, D>(lds, tb, t, items, ybuf, out, tid, 128);
                 break;
             case K65536B:
                 run_rows<Sh256c, PRow256, D>(lds, tb, t, items, ybuf, out, tid, 256);
@@ -214,6 +208,30 @@ __global__ void __launch_bounds__(kThreads)
             }
             __syncthreads();  // LDS and s_task reuse by the next task
         }
+    }
+}
+
+// The wide tiles: one 16384-point segment per 512-thread workgroup tile,
+// items [0, n) of the wide range, grid-stride (every wide tile is the same
+// size, so no cursor is needed).
+using ShWide = Shape<16384, 512, Radices<16, 32, 32>>;
+using PWide = SinglePassPolicy<ShWide, 1, 4, true, 0, false, 4, false, false, false, true>;
+
+template <int D>
+__global__ void __launch_bounds__(PWide::kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+    worklist_wide_kernel(const Item *__restrict__ items, uint32_t n, const c32 *__restrict__ tw,
+                         const c32 *in, c32 *out)
+{
+    __shared__ float lds[PWide::kLdsElems];
+    using S0 = Stage<ShWide, 0, 1>;
+    for (uint32_t g = blockIdx.x; g < n; g += gridDim.x) {
+        const int tid = opaque(threadIdx.x);  // as in single_pass_split_kernel
+        const Item it = items[g];
+        const c32 *x = in + it.in_off;
+        const typename PWide::Ctx ctx{out + it.out_off, true};
+        c32 v[ShWide::kMaxE];
+        st_gather<S0, ShWide>(v, tid, [&](int i) { return gload<true>(x + i); });
+        tile_run_split<ShWide, PWide, D, 0, 1>(v, lds, tw, tid, threadIdx.x, ctx);
     }
 }
 
@@ -232,6 +250,7 @@ __global__ void __launch_bounds__(256) clear_kernel(uint32_t *ctl, uint32_t n)
 struct LengthInfo {
     uint32_t n;
     bool two_pass;
+    bool wide;    // one-pass tile of its own launch (worklist_wide_kernel)
     Kind a, b;    // single pass: a only
     int per_tile; // single pass: segments per tile (S); two pass: blocks per pass
     int group;    // tiles (blocks) per task
@@ -239,15 +258,15 @@ struct LengthInfo {
 };
 
 const LengthInfo kLengths[] = {
-    {256, false, K256, K256, P256::S, 2, 0, 0},
-    {1000, false, K1000, K1000, P1000::S, 4, 0, 0},
-    {1024, false, K1024, K1024, P1024::S, 2, 0, 0},
-    {1536, false, K1536, K1536, P1536::S, 3, 0, 0},
-    {4096, false, K4096, K4096, P4096::S, 2, 0, 0},
-    {6000, false, K6000, K6000, P6000::S, 2, 0, 0},
-    {16384, true, K16384A, K16384B, 128 / PCol128::C, 4, 128, 128},
-    {65536, true, K65536A, K65536B, 256 / PCol256::C, 8, 256, 256},
-    {1u << 20, true, K1MA, K1MB, 1024 / PCol1k::C, 16, 1024, 1024},
+    {256, false, false, K256, K256, P256::S, 2, 0, 0},
+    {1000, false, false, K1000, K1000, P1000::S, 4, 0, 0},
+    {1024, false, false, K1024, K1024, P1024::S, 2, 0, 0},
+    {1536, false, false, K1536, K1536, P1536::S, 3, 0, 0},
+    {4096, false, false, K4096, K4096, P4096::S, 2, 0, 0},
+    {6000, false, false, K6000, K6000, P6000::S, 2, 0, 0},
+    {16384, false, true, K16384W, K16384W, 1, 1, 0, 0},
+    {65536, true, false, K65536A, K65536B, 256 / PCol256::C, 8, 256, 256},
+    {1u << 20, true, false, K1MA, K1MB, 1024 / PCol1k::C, 16, 1024, 1024},
 };
 
 const LengthInfo *length_info(uint32_t n)
@@ -272,6 +291,9 @@ struct WorkList {
     bool in_place_ok = false;          // outputs hit no other entry's input
     uint32_t n_tasks = 0, n_first = 0;  // tasks; of which run in the first launch
     uint32_t n_two_pass = 0;            // two-pass segments
+    uint32_t wide_first = 0, n_wide = 0;  // items of the wide launch
+    unsigned wide_grid = 1;
+    const c32 *wide_tw = nullptr;        // its twiddle table (one of table_mem)
     uint64_t counts[wl::KCOUNT] = {};
     uint64_t samples = 0;
     size_t y_bytes = 0;
@@ -358,6 +380,8 @@ int wl_tables(WorkList *w)
         if (!L.two_pass) {
             if ((st = up(roots(L.n), &tables[L.a].tw)) != FFT_OK)
                 return st;
+            if (L.wide)
+                w->wide_tw = tables[L.a].tw;
             continue;
         }
         if ((st = up(roots((uint64_t)L.n1), &tables[L.a].tw)) != FFT_OK ||
@@ -492,13 +516,18 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     hitems.clear();
     hitems.reserve(n);
     std::vector<Task> a_tasks, s_tasks, b_tasks;
+    std::vector<Item> wide_items;
     uint64_t y_samples = 0;
     uint32_t two_pass = 0;
     uint64_t counts[KCOUNT] = {};
     for (int li = (int)NL - 1; li >= 0; --li) {
         const LengthInfo &L = kLengths[li];
         const auto &b = bucket[li];
-        if (L.two_pass) {
+        if (L.wide) {
+            for (uint32_t idx : b)
+                wide_items.push_back({items[idx].in_off, items[idx].out_off, 0});
+            counts[L.a] += b.size();
+        } else if (L.two_pass) {
             for (uint32_t idx : b) {
                 const uint32_t item = (uint32_t)hitems.size();
                 hitems.push_back({items[idx].in_off, items[idx].out_off, y_samples});
@@ -523,6 +552,9 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
             }
         }
     }
+    // the wide launch's items follow the task items
+    const uint32_t wide_first = (uint32_t)hitems.size();
+    hitems.insert(hitems.end(), wide_items.begin(), wide_items.end());
     tasks.reserve(a_tasks.size() + s_tasks.size() + b_tasks.size());
     tasks.insert(tasks.end(), a_tasks.begin(), a_tasks.end());
     tasks.insert(tasks.end(), s_tasks.begin(), s_tasks.end());
@@ -537,6 +569,8 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     w->n_tasks = (uint32_t)tasks.size();
     w->n_first = (uint32_t)(a_tasks.size() + s_tasks.size());
     w->n_two_pass = two_pass;
+    w->wide_first = wide_first;
+    w->n_wide = (uint32_t)wide_items.size();
     w->y_bytes = y_samples * sizeof(c32);
     std::memcpy(w->counts, counts, sizeof(counts));
     return FFT_OK;
@@ -621,22 +655,38 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
         return hip_error(e, "hipEventRecord");
     const void *k = w->dir < 0 ? (const void *)&worklist_kernel<-1> : (const void *)&worklist_kernel<1>;
     const unsigned g = grid_for(k, kThreads, std::max<uint64_t>(1, w->n_tasks), w->device, 1);
-    if (g != w->grid)
-        w->drop_graph();  // the captured launch has the old grid
+    const void *kw = w->dir < 0 ? (const void *)&worklist_wide_kernel<-1>
+                                : (const void *)&worklist_wide_kernel<1>;
+    const unsigned gw = grid_for(kw, PWide::kThreads, std::max<uint64_t>(1, w->n_wide), w->device,
+                                 kWideGridMult);
+    if (g != w->grid || gw != w->wide_grid)
+        w->drop_graph();  // the captured launches have the old grids
     w->grid = g;
+    w->wide_grid = gw;
     return set_ok();
 }
 
 int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
 {
     using namespace wl;
-    if (w->n_tasks == 0)
+    if (w->n_tasks == 0 && w->n_wide == 0)
         return set_ok();
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, w->d_ctl, 2u);
-    // launch 0: pass-A and single-pass tasks; launch 1: pass-B tasks
+    // launch 0: pass-A and single-pass tasks; then the wide tiles; launch 1:
+    // pass-B tasks
     const uint32_t first[2] = {0, w->n_first};
     const uint32_t count[2] = {w->n_first, w->n_tasks - w->n_first};
     for (int l = 0; l < 2; ++l) {
+        if (l == 1 && w->n_wide) {
+            if (w->dir < 0)
+                hipLaunchKernelGGL((worklist_wide_kernel<-1>), dim3(w->wide_grid),
+                                   dim3(PWide::kThreads), 0, s, w->d_items + w->wide_first,
+                                   w->n_wide, w->wide_tw, (const c32 *)in, (c32 *)out);
+            else
+                hipLaunchKernelGGL((worklist_wide_kernel<1>), dim3(w->wide_grid),
+                                   dim3(PWide::kThreads), 0, s, w->d_items + w->wide_first,
+                                   w->n_wide, w->wide_tw, (const c32 *)in, (c32 *)out);
+        }
         if (count[l] == 0)
             continue;
         const unsigned grid = std::min<unsigned>(w->grid, (count[l] + kClaim - 1) / kClaim);
@@ -661,7 +711,7 @@ int wl_check_io(WorkList *w, const void *in, void *out)
         return set_error(FFT_ERR_INVALID_ARG, "in_base/out_base must not be NULL");
     if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
         return set_error(FFT_ERR_ALIGNMENT, "bases must be 8-byte aligned");
-    if (w->n_tasks == 0)
+    if (w->n_tasks == 0 && w->n_wide == 0)
         return FFT_OK;
     if (in == out && !w->in_place_ok)
         return set_error(FFT_ERR_OVERLAP,
@@ -762,7 +812,7 @@ extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, 
     int st = wl_check_io(w, in_base, out_base);
     if (st != FFT_OK)
         return st;
-    if (w->n_tasks == 0)
+    if (w->n_tasks == 0 && w->n_wide == 0)
         return set_ok();
     hipError_t e;
     if (!w->graph_exec || w->graph_in != in_base || w->graph_out != out_base) {
@@ -825,6 +875,8 @@ extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
                      ",\"tasks\":" + std::to_string(w->n_tasks) +
                      ",\"first_launch_tasks\":" + std::to_string(w->n_first) +
                      ",\"two_pass_segments\":" + std::to_string(w->n_two_pass) +
+                     ",\"wide_segments\":" + std::to_string(w->n_wide) +
+                     ",\"wide_grid\":" + std::to_string(w->wide_grid) +
                      ",\"samples\":" + std::to_string(w->samples) +
                      ",\"scratch_bytes\":" + std::to_string(w->y_bytes) +
                      ",\"in_place_ok\":" + (w->in_place_ok ? "true" : "false") +

@@ -89,6 +89,38 @@ def test_mixed_lengths_every_segment(direction):
         assert np.all(e <= 2 * oracle.tolerance(n)), (n, e.max())
 
 
+def test_wide_tiles_alone():
+    """A list of only 16384-point segments: no work-list task at all, just
+    the launch of wide tiles (one 512-thread workgroup per segment), out of
+    place, replayed from a graph, and in place."""
+    import torch
+    lengths = np.full(37, 16384, np.int64)
+    announce("work list of wide tiles only")
+    in_off, total = packed(lengths, gap=5)
+    out_off, out_total = packed(lengths[::-1])
+    out_off = out_off[::-1].copy()
+    x = siggen.Signal(seed=14, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(out_total, dtype=torch.complex64, device="cuda")
+    with fs.WorkList(to_entries(in_off, out_off, lengths)) as wl:
+        d = wl.describe()
+        assert d["tasks"] == 0 and d["wide_segments"] == len(lengths)
+        assert d["scratch_bytes"] == 0
+        wl.exec(xd, yd)
+        wl.status()
+        y = yd.cpu().numpy()
+        check_all(x, y, in_off, out_off, lengths)
+        for _ in range(2):
+            yd.zero_()
+            wl.exec(xd, yd, graph=True)
+            wl.status()
+            assert np.array_equal(yd.cpu().numpy(), y)
+    with fs.WorkList(to_entries(in_off, in_off, lengths)) as wl:
+        wl.exec(xd, xd)
+        wl.status()
+    check_all(x, xd.cpu().numpy(), in_off, in_off, lengths)
+
+
 def test_in_place_and_overlap_rules():
     import torch
     lengths = np.array([4096, 65536, 256, 16384, 1000, 6000, 1536, 1024] * 3, np.int64)
