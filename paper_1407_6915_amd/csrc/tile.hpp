@@ -831,10 +831,14 @@ struct FourStepCtx {
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
+          bool Wrap_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
+    // Wrap: tile columns are first + c modulo the (power-of-two) column
+    // count, so blocks may start at any column and the last one wraps
+    static constexpr bool kWrap = Wrap_;
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
     static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
@@ -865,7 +869,8 @@ struct ColumnPolicy {
     {
         if (!ctx.valid)
             return;
-        const unsigned n2 = (unsigned)(ctx.first + c);
+        const unsigned n2 = kWrap ? (unsigned)((ctx.first + c) & (ctx.n2 - 1))
+                                  : (unsigned)(ctx.first + c);
         const unsigned mask = (1u << ctx.sh) - 1u;
 #pragma unroll
         for (int u = 0; u < St::U; ++u) {
@@ -897,7 +902,7 @@ __device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw
     const int t = Pol::template thr<0>(tid);
     c32 v[Sh::kMaxE];
     using S0 = Stage<Sh, 0, 1>;
-    const c32 *xc = x + first + c;
+    const c32 *xc = x + (Pol::kWrap ? ((first + c) & (n2 - 1)) : (first + c));
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
     if constexpr (Pol::kSplit)
         tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
@@ -932,10 +937,12 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
-          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false>
+          bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
+          bool Wrap_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
+    static constexpr bool kWrap = Wrap_;    // as in ColumnPolicy (rows modulo n1)
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
     static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
@@ -973,7 +980,7 @@ struct RowPolicy {
     {
         if (!ctx.valid)
             return;
-        c32 *y = ctx.y + ctx.first + c;
+        c32 *y = ctx.y + (kWrap ? ((ctx.first + c) & (ctx.n1 - 1)) : (ctx.first + c));
 #pragma unroll
         for (int u = 0; u < St::U; ++u) {
             const int b = t + u * Sh::T;
@@ -998,7 +1005,7 @@ __device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, i
     const int t = Pol::template thr<0>(tid);
     c32 v[Sh::kMaxE];
     using S0 = Stage<Sh, 0, 1>;
-    const c32 *yr = y + (size_t)(first + c) * Sh::M;
+    const c32 *yr = y + (size_t)(Pol::kWrap ? ((first + c) & (n1 - 1)) : (first + c)) * Sh::M;
     st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
     if constexpr (Pol::kSplit)
         tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,

@@ -57,7 +57,8 @@ struct Task {
     uint32_t count;   // single pass: segments in the task (whole tiles of S)
     uint32_t tile;    // two pass: first column/row block
     uint32_t ntiles;  // two pass: blocks in the task
-    uint32_t pad[3];
+    uint32_t shift;   // two pass: column (pass A) / row (pass B) where block 0 starts
+    uint32_t pad[2];
 };
 
 struct Tables {      // per kind, device pointers
@@ -83,11 +84,11 @@ using P4096 = SinglePassPolicy<Sh4096, 1, 4, true, 0, false>;
 using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
 using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false>;
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
-using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0>;
-using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0>;
+using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
+using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
 using Sh1k = Shape<1024, 64, Radices<16, 16, 4>>;
-using PCol1k = ColumnPolicy<Sh1k, 4, 4, true, 0>;
-using PRow1k = RowPolicy<Sh1k, 4, 4, true, 0>;
+using PCol1k = ColumnPolicy<Sh1k, 4, 4, true, 0, false, 1, false, false, true>;
+using PRow1k = RowPolicy<Sh1k, 4, 4, true, 0, false, 1, false, false, true>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLdsElems =
@@ -108,6 +109,8 @@ static_assert(PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
 constexpr uint32_t kClaim = 4;
 // persistent grid of the wide launch: resident workgroup waves per CU
 constexpr int kWideGridMult = 32;
+// samples per 128-byte cache line
+constexpr uint64_t kLine = 16;
 
 // a value the compiler must recompute per loop iteration (see below)
 __device__ __forceinline__ int opaque(int v)
@@ -142,7 +145,7 @@ __device__ __forceinline__ void run_columns(c32 *lds, const Tables &tb, const Ta
     for (uint32_t k = 0; k < t.ntiles; ++k) {
         const int tid = opaque(tid0);
         column_tile<Sh, Pol, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, tid, in + it.in_off,
-                                ybuf + it.y_off, (int)(t.tile + k) * Pol::C, n2);
+                                ybuf + it.y_off, (int)((t.tile + k) * Pol::C + t.shift), n2);
     }
 }
 
@@ -155,12 +158,12 @@ __device__ __forceinline__ void run_rows(c32 *lds, const Tables &tb, const Task 
     for (uint32_t k = 0; k < t.ntiles; ++k) {
         const int tid = opaque(tid0);
         row_tile<Sh, Pol, D>(lds, tb.tw, tid, tid, ybuf + it.y_off, out + it.out_off,
-                             (int)(t.tile + k) * Pol::C, n1);
+                             (int)((t.tile + k) * Pol::C + t.shift), n1);
     }
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
     worklist_kernel(const Task *__restrict__ tasks, uint32_t n_tasks,
                     const Item *__restrict__ items, const Tables *__restrict__ tables,
                     const c32 *in, c32 *out, c32 *ybuf, uint32_t *cursor)
@@ -530,12 +533,25 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
         } else if (L.two_pass) {
             for (uint32_t idx : b) {
                 const uint32_t item = (uint32_t)hitems.size();
-                hitems.push_back({items[idx].in_off, items[idx].out_off, y_samples});
-                y_samples += L.n;
+                // Segments may start anywhere in a 128-byte line (16
+                // samples).  Column blocks then start at the first column
+                // whose address is line-aligned, so every block reads and
+                // writes whole lines (the last block wraps round to columns
+                // 0..shift-1, whose pieces pair up into lines with those of
+                // the neighbouring rows); Y gets the input's offset within
+                // a line, and the row blocks of pass B start where the
+                // output's rows do.
+                const uint64_t in_m = items[idx].in_off % kLine,
+                               out_m = items[idx].out_off % kLine;
+                const uint64_t y_off = (y_samples + kLine - 1) / kLine * kLine + in_m;
+                hitems.push_back({items[idx].in_off, items[idx].out_off, y_off});
+                y_samples = y_off + L.n;
+                const uint32_t sa = (uint32_t)((kLine - in_m) % kLine),
+                               sb = (uint32_t)((kLine - out_m) % kLine);
                 for (int t = 0; t < L.per_tile; t += L.group) {
                     const uint32_t nt = (uint32_t)std::min(L.group, L.per_tile - t);
-                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, nt, {0, 0, 0}});
-                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, nt, {0, 0, 0}});
+                    a_tasks.push_back({(uint32_t)L.a, item, 1, (uint32_t)t, nt, sa, {0, 0}});
+                    b_tasks.push_back({(uint32_t)L.b, item, 1, (uint32_t)t, nt, sb, {0, 0}});
                 }
                 counts[L.a] += 1;
                 ++two_pass;
@@ -547,7 +563,7 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
                 const uint32_t cnt = (uint32_t)std::min<size_t>(per_task, b.size() - k);
                 for (uint32_t j = 0; j < cnt; ++j)
                     hitems.push_back({items[b[k + j]].in_off, items[b[k + j]].out_off, 0});
-                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, {0, 0, 0}});
+                s_tasks.push_back({(uint32_t)L.a, first, cnt, 0, 0, 0, {0, 0}});
                 counts[L.a] += cnt;
             }
         }
