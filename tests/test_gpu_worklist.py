@@ -121,6 +121,28 @@ def test_wide_tiles_alone():
     check_all(x, xd.cpu().numpy(), in_off, in_off, lengths)
 
 
+@pytest.mark.parametrize("lead", [0, 8, 3, 13])
+def test_two_pass_segments_at_any_line_offset(lead):
+    """Two-pass segments (65536 and 2^20 points) whose inputs and outputs
+    start at every kind of offset within a 128-byte line: the column and row
+    blocks then start mid-segment and the last one wraps round."""
+    import torch
+    lengths = np.array([65536, 1 << 20, 65536, 65536], np.int64)
+    announce("work list two-pass segments, lead %d samples" % lead)
+    in_off, total = packed(lengths, gap=5)
+    in_off = in_off + lead
+    out_off, out_total = packed(lengths[::-1], gap=7)
+    out_off = out_off[::-1].copy() + (lead * 3) % 16
+    x = siggen.Signal(seed=15, seg_len=1, sigma=1.0).samples(0, total + lead)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(out_total + 16, dtype=torch.complex64, device="cuda")
+    for direction in (fs.FORWARD, fs.INVERSE):
+        with fs.WorkList(to_entries(in_off, out_off, lengths), direction) as wl:
+            wl.exec(xd, yd)
+            wl.status()
+        check_all(x, yd.cpu().numpy(), in_off, out_off, lengths, direction)
+
+
 def test_in_place_and_overlap_rules():
     import torch
     lengths = np.array([4096, 65536, 256, 16384, 1000, 6000, 1536, 1024] * 3, np.int64)
