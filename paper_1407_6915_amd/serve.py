@@ -98,6 +98,7 @@ class SimExecutor:
         self.busy = {"in": 0.0, "comp": 0.0, "out": 0.0}
         self.ends: List[float] = []           # completion times not yet reached
         self.launches: List[List[int]] = []  # job indices per compute launch
+        self.issued: List[float] = []        # clock time each launch was issued
         self.max_launch_samples = 0
 
     def now(self) -> float:
@@ -112,12 +113,14 @@ class SimExecutor:
     def h2d(self, job: JobState):
         return self._enqueue("in", job.samples * SAMPLE_BYTES / self.link)
 
-    def compute(self, jobs: List[JobState]):
+    def compute(self, jobs: List[JobState], after=None):
         samples = sum(j.samples for j in jobs)
         self.max_launch_samples = max(self.max_launch_samples, samples)
         self.launches.append([j.index for j in jobs])
-        passes = sum(j.samples * (2 if j.seg_len > 6000 else 1) for j in jobs)
-        return self._enqueue("comp", self.launch + 16.0 * passes / self.hbm)
+        self.issued.append(self.t)
+        passes = sum(j.samples * (2 if j.seg_len > 16384 else 1) for j in jobs)
+        return self._enqueue("comp", self.launch + 16.0 * passes / self.hbm,
+                             0.0 if after is None else after)
 
     def d2h(self, job: JobState, after):
         return self._enqueue("out", job.samples * SAMPLE_BYTES / self.link, after)
@@ -208,7 +211,7 @@ class GpuExecutor:
         dst = self.base + job.off * SAMPLE_BYTES
         return self._copy(self.s_in, "h2d", (dst, job.host_in), job.samples * SAMPLE_BYTES)
 
-    def compute(self, jobs: List[JobState]):
+    def compute(self, jobs: List[JobState], after=None):
         import numpy as np
         torch = self.torch
         n = sum(j.n_seg for j in jobs)
@@ -225,6 +228,8 @@ class GpuExecutor:
         self.launches.append([j.index for j in jobs])
         self.max_launch_samples = max(self.max_launch_samples, sum(j.samples for j in jobs))
         sh = self.s_comp.cuda_stream
+        if after is not None:
+            self.s_comp.wait_event(after)  # e.g. the job's own input copy
         self.wl.reset(ent, stream=sh)
         self.wl.exec_ptr(self.base, self.base, sh)
         ev = torch.cuda.Event()
@@ -324,6 +329,21 @@ def serve(jobs: List[JobState], executor, arena_samples: int,
             copying.append(head)
             peak_used = max(peak_used, arena.used)
             progressed = True
+            # A lone job on an idle device goes to the transform stream at
+            # once, behind its own copy (the stream waits for the copy on
+            # the device): at light load it pays no host round trip between
+            # copy and transform, and its work list is compiled while the
+            # copy runs.  Jobs that arrive meanwhile wait for the next
+            # launch, as they would have anyway.
+            if len(copying) == 1 and not ready and not pending and executor.stream_idle():
+                j = copying.popleft()
+                tok = executor.compute([j], after=j.tokens["in"])
+                j.status = "computing"
+                j.launch = launch_id
+                j.tokens["comp"] = tok
+                j.tokens["out"] = executor.d2h(j, tok)
+                returning.append(j)
+                launch_id += 1
         # inputs that have landed
         while copying and executor.done(copying[0].tokens["in"]):
             j = copying.popleft()

@@ -86,6 +86,23 @@ def test_continuous_batching_packs_under_load():
     assert max(len(l) for l in ex2.launches) > 1
 
 
+def test_lone_job_is_dispatched_behind_its_copy():
+    """At light load each job goes to the transform stream when it is
+    admitted, ordered after its own copy on the device, so its latency is
+    exactly copy in + transform + copy out."""
+    jobs = jobs_from(1.0, 50)
+    ex = SimExecutor(link_gbs=50, hbm_gbs=5000, launch_us=10)
+    serve(jobs, ex, 1 << 40)
+    assert len(ex.launches) == 50
+    for j, launch, t_issue in zip(jobs, ex.launches, ex.issued):
+        assert launch == [j.index]
+        assert t_issue == pytest.approx(j.admitted_s)
+        link = j.samples * 8 / 50e9
+        passes = j.samples * (2 if j.seg_len > 16384 else 1)
+        expect = 2 * link + 10e-6 + 16.0 * passes / 5000e9
+        assert j.done_s - j.arrival_s == pytest.approx(expect, rel=1e-9, abs=1e-12)
+
+
 def test_small_budget_serialises_but_completes():
     jobs = [JobState(i, 0.001 * i, 4096, 256) for i in range(40)]   # 1M samples each
     ex = SimExecutor()
