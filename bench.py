@@ -177,6 +177,19 @@ def bench_large(args):
         torch.cuda.synchronize()
         out["copy_reference_GBps"] = round(alg_bytes / (c0.elapsed_time(c1) / args.steps / 1e3)
                                            / 1e9, 1)
+        # the library's own streaming copy (the identity transform of
+        # length 1) over the same 8 GiB: the fastest plain copy measured here
+        with fs.Plan(1, samples) as ident:
+            for _ in range(2):
+                ident.exec_ptr(xd.data_ptr(), yd.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            c0.record(stream)
+            for _ in range(args.steps):
+                ident.exec_ptr(xd.data_ptr(), yd.data_ptr(), stream.cuda_stream)
+            c1.record(stream)
+            torch.cuda.synchronize()
+        out["copy_kernel_GBps"] = round(alg_bytes / (c0.elapsed_time(c1) / args.steps / 1e3)
+                                        / 1e9, 1)
     plan.close()
     del xd, yd
     torch.cuda.synchronize()

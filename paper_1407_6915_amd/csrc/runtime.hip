@@ -536,6 +536,53 @@ int check_io(const void *in, const void *out, uint64_t bytes)
 }
 
 // ---------------------------------------------------------------------------
+// Identity transform (segment length 1) as a streaming copy.  Each
+// workgroup moves one tile of 256 x K accesses, all loads issued before the
+// stores, non-temporal; 16-byte accesses when both pointers allow them and
+// the sample count is even, else 8-byte ones.  The dynamic LDS of each
+// launch is not used: it holds residency at 3 workgroups per CU, which
+// measured faster (5.8 TB/s) than the 8 the registers allow (5.4 TB/s) or
+// a device-to-device hipMemcpyAsync (4.3 TB/s).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+constexpr unsigned kCopyLds = 48 * 1024;
+
+template <class T, int K>
+__global__ void __launch_bounds__(256)
+    identity_copy_kernel(const T *__restrict__ in, T *__restrict__ out, uint64_t n)
+{
+    extern __shared__ float unused_lds[];
+    const uint64_t tile = 256ull * K;
+    for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
+        T v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t i = base + threadIdx.x + 256ull * k;
+            if (i < n)
+                v[k] = __builtin_nontemporal_load(in + i);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t i = base + threadIdx.x + 256ull * k;
+            if (i < n)
+                __builtin_nontemporal_store(v[k], out + i);
+        }
+    }
+    if (n == UINT64_MAX)  // never true: keeps the (unused) allocation referenced
+        unused_lds[threadIdx.x] = 0.f;
+}
+
+template <class T, int K>
+int identity_copy(const void *in, void *out, uint64_t n, hipStream_t s)
+{
+    const uint64_t tiles = (n + 256ull * K - 1) / (256ull * K);
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 0x7fffffffull));
+    hipLaunchKernelGGL((identity_copy_kernel<T, K>), dim3(grid), dim3(256), kCopyLds, s,
+                       (const T *)in, (T *)out, n);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FFT_OK : hip_error(e, "identity copy");
+}
+
 // enqueue the transform of `batch` segments (arguments already checked)
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s)
 {
@@ -544,10 +591,11 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
     switch (p->kind) {
     case Plan::COPY:
         if (in != out) {
-            hipError_t e = hipMemcpyAsync(out, in, batch * sizeof(c32),
-                                          hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess)
-                return hip_error(e, "identity copy");
+            const bool wide = ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0) && !(batch & 1);
+            const int st = wide ? identity_copy<f4v, 8>(in, out, batch / 2, s)
+                                : identity_copy<f2v, 16>(in, out, batch, s);
+            if (st != FFT_OK)
+                return st;
         }
         break;
     case Plan::SINGLE: {

@@ -188,6 +188,20 @@ def test_length_one_is_identity():
     x = noise(1, 10, seed=5)
     assert np.array_equal(run(1, x), x)
     assert np.array_equal(run(1, x, fs.INVERSE), x)
+    # the copy kernel's cases: 16-byte accesses (even count, aligned), 8-byte
+    # accesses (odd count, or a pointer off a 16-byte boundary), several
+    # workgroup tiles with a ragged last one
+    import torch
+    for b, lead in [(2 * 2048 * 3 + 2, 0), (2048 * 5 + 3, 0), (4096 * 2 + 6, 1)]:
+        x = noise(1, b + lead, seed=b).reshape(-1)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros(b + 1, dtype=torch.complex64, device="cuda")
+        with fs.Plan(1, b) as p:
+            p.exec_ptr(xd.data_ptr() + 8 * lead, yd.data_ptr() + 8 * lead, 0)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+        assert np.array_equal(y[lead:lead + b], x[lead:lead + b])
+        assert np.all(y[:lead] == 0) and np.all(y[lead + b:] == 0)
 
 
 def test_zero_input_gives_exact_zero():
