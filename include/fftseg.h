@@ -203,8 +203,9 @@ int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
  *   window  device, segment_len float32 values, 4-byte aligned, or NULL
  * 1 <= n_frames <= the plan's batch and hop >= 1, else
  * FFT_ERR_INVALID_ARG.  Lengths with a one-pass kernel read the frames in
- * place; other lengths gather the windowed frames into out first and
- * transform out in place. */
+ * place (with the plan's own kernel variant when it has a frame form, else
+ * the length's default frame kernel); other lengths gather the windowed
+ * frames into out first and transform out in place. */
 int fft_exec_frames(fft_plan_t plan, const void *in, size_t in_len, void *out,
                     size_t n_frames, size_t hop, const float *window, void *stream);
 

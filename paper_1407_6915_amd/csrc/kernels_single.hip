@@ -41,8 +41,10 @@ const SinglePassDesc kTable[] = {
     SpInst<2048, 128, 2, 4, kClassic, 16, 16, 8>::desc(3, 32),
     SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 64),
     SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
+    // (variant 3 first: the length's frame and real-input kernels are the
+    // first row with them)
+    SpInst<4096, 256, 1, 0, kNT | kPlain | kAux, 16, 16, 16>::desc(3, 32),
     SpInst<4096, 512, 1, 4, kNT | kPlain | kAux, 8, 8, 8, 8>::desc(2, 64),
-    SpInst<4096, 256, 1, 0, kNT | kPlain, 16, 16, 16>::desc(3, 32),
     SpInst<4096, 128, 2, 0, kNT | kPlain, 16, 16, 16>::desc(4, 32),
     SpInst<4096, 256, 1, 4, kPlain, 16, 16, 16>::desc(5, 32),
     SpInst<4096, 256, 1, 0, kClassic | kNT, 16, 16, 16>::desc(6, 32),

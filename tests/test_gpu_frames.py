@@ -52,6 +52,24 @@ def test_frames_match_oracle(n, hop, frames, windowed):
     assert np.all(err <= oracle.tolerance(n)), err.max()
 
 
+def test_frames_with_every_4096_variant():
+    """A plan forced to a kernel variant uses that variant's frame form when
+    it has one and the length's default frame kernel otherwise: all agree
+    with the oracle."""
+    n, hop, frames = 4096, 1536, 19
+    x = siggen.Signal(seed=44, seg_len=1, sigma=1.0).samples(0, (frames - 1) * hop + n)
+    w = hann32(n)
+    ref = oracle.short_time(x, n, hop, frames, w)
+    import torch
+    xd = torch.from_numpy(x).to("cuda")
+    wd = torch.from_numpy(w).to("cuda")
+    for v in range(fs.variant_count(n)):
+        announce("frames n=%d variant %d" % (n, v))
+        with fs.Plan(n, frames, fs.FORWARD, v) as p:
+            y = p.exec_frames(xd, hop, frames, wd).cpu().numpy().reshape(frames, n)
+        assert np.all(oracle.rel_l2(y, ref) <= oracle.tolerance(n)), v
+
+
 def test_frames_inverse_and_smaller_than_plan():
     n, hop, frames = 2048, 512, 13
     announce("frames inverse n=%d" % n)
