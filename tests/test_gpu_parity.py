@@ -123,6 +123,17 @@ def test_every_four_step_tile_variant(n):
                 assert np.all(e <= oracle.tolerance(n)), (c, r, d, e.max())
 
 
+@pytest.mark.parametrize("n", [1 << 21, 3 * (1 << 20), 1 << 23, 1 << 24])
+def test_long_lengths_up_to_the_cap(n):
+    """Segments up to the 2^24-sample cap (two passes where both halves
+    have tiles, the radix-stage path otherwise), both directions."""
+    b = 2 if n <= 1 << 21 else 1
+    announce("n=%d batch=%d (%s)" % (n, b, fs.Plan(n, b).describe()["kind"]))
+    x = noise(n, b, seed=n + 5)
+    for d in (fs.FORWARD, fs.INVERSE):
+        check(n, run(n, x, d), x, d, what="long dir %d" % d)
+
+
 @pytest.mark.parametrize("n", [1024, 4096, 6000, 1 << 16, 3 ** 9, 5])
 def test_in_place_equals_out_of_place_and_deterministic(n):
     b = ragged_batch(n)
