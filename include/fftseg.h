@@ -84,8 +84,8 @@ typedef struct fftseg_plan *fft_plan_t;
 fft_plan_t fft_plan_create(size_t segment_len, size_t batch, int direction);
 
 /* Plan for real-input segments (the float32 samples of Sec. III, 4 bytes
- * each).  segment_len = N must be even and N/2 a length with a one-pass
- * kernel (N = 4 .. 32768 powers of two, 2000, 3072, 12000); otherwise
+ * each).  segment_len = N must be even, at least 4, and a supported length
+ * (prime factors 2, 3, 5; at most 2^24); otherwise
  * FFT_ERR_UNSUPPORTED_LENGTH.  Executed by fft_exec_segments /
  * fft_exec_segments_n, always out of place (in and out must not overlap,
  * else FFT_ERR_OVERLAP):
@@ -99,10 +99,14 @@ fft_plan_t fft_plan_create(size_t segment_len, size_t batch, int direction);
  *                     with X_s[N-k] = conj X_s[k], unnormalised; the
  *                     imaginary parts of bins 0 and N/2 are ignored.
  * Both buffers must be 8-byte aligned.  The N reals are transformed as
- * N/2 complex values z[m] = x[2m] + i x[2m+1] by the one-pass kernel, with
- * the split into even and odd parts fused into its store (forward) or
- * load (inverse), so each byte crosses HBM once.  Streaming, frames, graph
- * and work-list entry points take complex plans only. */
+ * N/2 complex values z[m] = x[2m] + i x[2m+1].  Where N/2 has a one-pass
+ * kernel the split into even and odd parts is fused into its store
+ * (forward) or load (inverse), so each byte crosses HBM once.  Other even
+ * lengths run the N/2-point complex plan (two passes or radix stages) and
+ * the split as a separate pass through a buffer of up to 2 GiB of N/2-point
+ * rows (plus that plan's own scratch; fft_plan_scratch_bytes reports both).
+ * Streaming, frames, graph and work-list entry points take complex plans
+ * only. */
 fft_plan_t fft_plan_create_real(size_t segment_len, size_t batch, int direction);
 
 /* Transform every segment: the record at byte offset s*segment_len*8 of

@@ -443,26 +443,45 @@ int plan_build_real(Plan *p, uint64_t n, uint64_t batch, int dir)
         return set_error(FFT_ERR_HIP, "no HIP device available");
     }
     const uint64_t m = n / 2;
-    p->sp = find_aux(m);
-    if (!p->sp || !p->sp->launch_real)
-        return set_error(FFT_ERR_UNSUPPORTED_LENGTH,
-                         "real segments of length %llu need a one-pass kernel of length %llu",
-                         (unsigned long long)n, (unsigned long long)m);
-    p->kind = Plan::REAL;
-    p->grid_mult = p->sp->grid_mult;
     std::vector<c32> hw(m + 1);
     for (uint64_t k = 0; k <= m; ++k)
         hw[k] = root_forward(k, n);
     hipError_t e;
-    if ((e = upload(root_table(m), &p->tw)) != hipSuccess || (e = upload(hw, &p->tw2)) != hipSuccess)
+    p->sp = find_aux(m);
+    if (p->sp && p->sp->launch_real) {
+        // the split fused into the m-point one-pass kernel
+        p->kind = Plan::REAL;
+        p->grid_mult = p->sp->grid_mult;
+        if ((e = upload(root_table(m), &p->tw)) != hipSuccess ||
+            (e = upload(hw, &p->tw2)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+        return set_ok();
+    }
+    // the m-point complex plan over sub-batches, the split as its own pass
+    p->sp = nullptr;
+    p->kind = Plan::REAL_SPLIT;
+    const uint64_t max_sub_samples = 1ull << 28;  // 2 GiB of complex64 in the split buffer
+    p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / m));
+    p->inner = new Plan();
+    if (plan_build(p->inner, m, p->sub_batch, dir, -1) != FFT_OK)
+        return last_status();
+    if ((e = upload(hw, &p->tw2)) != hipSuccess)
         return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
                                         : hip_error(e, "twiddle upload");
+    const size_t zb = p->sub_batch * m * sizeof(c32);
+    if ((e = hipMalloc(&p->zbuf, zb)) != hipSuccess) {
+        p->zbuf = nullptr;
+        (void)hipGetLastError();
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "split buffer of %zu bytes", zb);
+    }
+    p->scratch_bytes = zb + p->inner->scratch_bytes;
     return set_ok();
 }
 
 int reject_real(const Plan *p, const char *what)
 {
-    if (p && p->kind == Plan::REAL)
+    if (p && is_real(p))
         return set_error(FFT_ERR_INVALID_ARG, "%s takes complex plans; real plans run through"
                          " fft_exec_segments", what);
     return FFT_OK;
@@ -472,9 +491,14 @@ void plan_free(Plan *p)
 {
     if (p->used && p->last_stream_valid)
         (void)hipStreamSynchronize(p->last_stream);
-    for (void *q : {p->tw, p->tw2, p->tl, p->th, p->scratch})
+    for (void *q : {p->tw, p->tw2, p->tl, p->th, p->scratch, p->zbuf})
         if (q)
             (void)hipFree(q);
+    if (p->inner) {
+        plan_free(p->inner);
+        delete p->inner;
+        p->inner = nullptr;
+    }
     stream_state_free(p);
     if (p->graph_exec)
         (void)hipGraphExecDestroy(p->graph_exec);
@@ -485,7 +509,7 @@ void plan_free(Plan *p)
     p->graph_exec = nullptr;
     p->graph = nullptr;
     p->capture_stream = nullptr;
-    p->tw = p->tw2 = p->tl = p->th = p->scratch = nullptr;
+    p->tw = p->tw2 = p->tl = p->th = p->scratch = p->zbuf = nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,6 +638,27 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
         d->launch_real(dir, in, out, p->tw, p->tw2, batch, grid, s);
         break;
     }
+    case Plan::REAL_SPLIT: {
+        const uint64_t m = n / 2;
+        for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch) {
+            const uint64_t sb = std::min(p->sub_batch, batch - s0);
+            int st;
+            if (dir < 0) {
+                // n floats per row in = m complex; m + 1 complex per row out
+                if ((st = plan_enqueue(p->inner, (const c32 *)in + s0 * m, p->zbuf, sb, s)) !=
+                        FFT_OK ||
+                    (st = real_split_enqueue(dir, p->zbuf, (c32 *)out + s0 * (m + 1), p->tw2, m,
+                                             sb, s)) != FFT_OK)
+                    return st;
+            } else {
+                if ((st = real_split_enqueue(dir, (const c32 *)in + s0 * (m + 1), p->zbuf,
+                                             p->tw2, m, sb, s)) != FFT_OK ||
+                    (st = plan_enqueue(p->inner, p->zbuf, (c32 *)out + s0 * m, sb, s)) != FFT_OK)
+                    return st;
+            }
+        }
+        break;
+    }
     case Plan::FOURSTEP: {
         const ColumnDesc *cd = p->col;
         const RowDesc *rd = p->row;
@@ -721,6 +766,17 @@ int plan_describe(const Plan *p, std::string &js)
                  (unsigned long long)(p->n / 2), rad(p->sp->radices, p->sp->nrad).c_str(),
                  p->sp->threads, p->sp->segs_per_wg, p->grid_mult);
         break;
+    case Plan::REAL_SPLIT: {
+        std::string inner;
+        plan_describe(p->inner, inner);
+        js = "{\"kind\":\"real\",\"n\":" + std::to_string(p->n) +
+             ",\"batch\":" + std::to_string(p->batch) + ",\"direction\":" +
+             std::to_string(p->dir) + ",\"complex_length\":" + std::to_string(p->n / 2) +
+             ",\"separate_split\":1,\"sub_batch\":" + std::to_string(p->sub_batch) +
+             ",\"scratch_bytes\":" + std::to_string(p->scratch_bytes) +
+             ",\"complex_plan\":" + inner + "}";
+        return FFT_OK;
+    }
     case Plan::GENERIC:
         snprintf(buf, sizeof buf,
                  "{\"kind\":\"radix_stages\",\"n\":%llu,\"batch\":%llu,\"direction\":%d,"
@@ -916,7 +972,7 @@ extern "C" int fft_exec_segments_n(fft_plan_t plan, const void *in, void *out,
         return set_error(FFT_ERR_INVALID_ARG, "batch %zu outside [1, %llu]", batch,
                          (unsigned long long)p->batch);
     int st;
-    if (p->kind == Plan::REAL) {
+    if (is_real(p)) {
         // forward: n floats in, n/2+1 complex out; inverse the other way round
         const uint64_t rb = (uint64_t)batch * p->n * sizeof(float);
         const uint64_t cb = (uint64_t)batch * (p->n / 2 + 1) * sizeof(c32);

@@ -14,7 +14,7 @@
 namespace fftseg {
 
 struct Plan {
-    enum Kind { COPY, SINGLE, FOURSTEP, GENERIC, REAL };
+    enum Kind { COPY, SINGLE, FOURSTEP, GENERIC, REAL, REAL_SPLIT };
     uint64_t n = 0, batch = 0;
     int dir = -1;
     int device = 0;
@@ -42,7 +42,13 @@ struct Plan {
     void *graph_out = nullptr;
     hipStream_t capture_stream = nullptr;
     void *stream_state = nullptr;  // pinned host ring of the streaming path
+    // REAL_SPLIT: the complex n/2-point plan (batch = sub_batch) and the
+    // buffer of its spectra (forward) or inputs (inverse), sub_batch rows
+    Plan *inner = nullptr;
+    void *zbuf = nullptr;
 };
+
+inline bool is_real(const Plan *p) { return p->kind == Plan::REAL || p->kind == Plan::REAL_SPLIT; }
 
 int set_ok();
 int set_error(int status, const char *fmt, ...);
@@ -67,8 +73,11 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
                int forced_split_variants = -1);
 void plan_free(Plan *p);
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
-// real-input plans: length n = 2m through the m-point one-pass kernel
+// real-input plans: length n = 2m through the m-point one-pass kernel, or,
+// where m has none, through the m-point complex plan and a separate split pass
 int plan_build_real(Plan *p, uint64_t n, uint64_t batch, int dir);
+int real_split_enqueue(int dir, const void *in, void *out, const void *hw, uint64_t m,
+                       uint64_t batch, hipStream_t s);
 // entry points that only take complex segments refuse real plans
 int reject_real(const Plan *p, const char *what);
 int plan_describe(const Plan *p, std::string &js);

@@ -1,6 +1,8 @@
 """Real-input segments (fft_plan_create_real) against the FP64 oracle:
 forward bins 0..N/2 of float32 segments, inverse back to float32 samples,
-every length with a real kernel, ragged batches, argument errors."""
+every length with a fused real kernel and lengths whose half runs as a
+two-pass or radix-stage plan with a separate split pass, ragged batches,
+argument errors."""
 import ctypes
 
 import numpy as np
@@ -16,6 +18,9 @@ pytestmark = pytest.mark.gpu
 
 REAL_LENGTHS = [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768,
                 2000, 3072, 12000]
+# N/2 without a one-pass kernel: four-step (65536, 2^17, 2^21) or radix
+# stages (2 * 3^9, 2 * 5^6)
+SPLIT_LENGTHS = [1 << 16, 1 << 17, 1 << 21, 2 * 3 ** 9, 2 * 5 ** 6]
 
 
 def real_samples(n, batch, seed):
@@ -33,7 +38,7 @@ def run_real(n, batch, x, direction):
     return y.cpu().numpy()
 
 
-@pytest.mark.parametrize("n", REAL_LENGTHS)
+@pytest.mark.parametrize("n", REAL_LENGTHS + SPLIT_LENGTHS)
 def test_real_forward_and_inverse(n):
     batch = max(3, min(257, (1 << 21) // n)) | 1          # odd: ragged last tile
     announce("real n=%d batch=%d" % (n, batch))
@@ -79,7 +84,7 @@ def test_real_cosine_bins():
 def test_real_plan_errors():
     import torch
     announce("real plan errors")
-    for n in (7, 2, 2 * 7 * 64, 65536):
+    for n in (7, 2, 2 * 7 * 64, 1 << 25):
         with pytest.raises(fs.FFTError) as e:
             fs.RealPlan(n, 4)
         assert e.value.name == "FFT_ERR_UNSUPPORTED_LENGTH", n
@@ -113,3 +118,33 @@ def test_real_plan_errors():
                 assert e.value.name == "FFT_ERR_BOUNDS"
     finally:
         hip.hipFree(q)
+
+
+def test_real_separate_split_over_sub_batches():
+    """A separate-split plan whose batch spans two sub-batches (2^28 complex
+    values of the half length each): rows repeat with period 2, so the rows
+    of the second sub-batch must equal those of the first bit for bit, and
+    the first two match the oracle."""
+    import torch
+    n, batch = 1 << 21, 258
+    announce("real separate split n=%d batch=%d" % (n, batch))
+    with fs.RealPlan(n, batch) as p:
+        d = p.describe()
+        assert d["kind"] == "real" and d["separate_split"] == 1 and d["sub_batch"] == 256
+    x2 = real_samples(n, 2, 77)
+    xd = torch.from_numpy(x2).to("cuda").repeat(batch // 2)
+    with fs.RealPlan(n, batch, fs.FORWARD) as p:
+        y = p.exec(xd).reshape(batch, n // 2 + 1)
+    torch.cuda.synchronize()
+    assert torch.equal(y[256:258], y[0:2])
+    ref = oracle.real_forward(x2, n)
+    assert np.all(oracle.rel_l2(y[0:2].cpu().numpy(), ref) <= oracle.tolerance(n))
+    spec = torch.from_numpy(ref.astype(np.complex64).reshape(-1)).to("cuda").repeat(batch // 2)
+    with fs.RealPlan(n, batch, fs.INVERSE) as p:
+        back = p.exec(spec).reshape(batch, n)
+    torch.cuda.synchronize()
+    assert torch.equal(back[256:258], back[0:2])
+    want = oracle.real_inverse(ref.astype(np.complex64), n)
+    b2 = back[0:2].cpu().numpy()
+    e = np.linalg.norm(b2 - want, axis=1) / np.linalg.norm(want, axis=1)
+    assert np.all(e <= oracle.tolerance(n)), e.max()
