@@ -5,9 +5,11 @@
 // of the signal (hop < N overlaps consecutive frames) and is multiplied by a
 // real window before its transform, i.e. a short-time Fourier transform.
 // Lengths with an LDS-resident kernel read the frames directly through a
-// strided gather in the kernel's first stage, so the overlapping input is
-// read once per frame and nothing is staged; other lengths first gather the
-// windowed frames into the output buffer and transform it in place.
+// strided gather in the kernel's first stage, and two-pass lengths through
+// the column loads of their first pass, so the overlapping input is read
+// once per frame and nothing is staged; the radix-stage lengths first
+// gather the windowed frames into the output buffer and transform it in
+// place.
 #include "fftseg.h"
 #include "runtime.hpp"
 
@@ -53,6 +55,31 @@ int frames_enqueue(Plan *p, const c32 *in, c32 *out, uint64_t frames, uint64_t h
             p->last_stream_valid = true;
             return set_ok();
         }
+    }
+    if (p->kind == Plan::FOURSTEP && p->col->launch_frames) {
+        // the column pass reads the frames; the row pass as for segments
+        const ColumnDesc *cd = p->col;
+        const RowDesc *rd = p->row;
+        const int dir = p->dir;
+        for (uint64_t s0 = 0; s0 < frames; s0 += p->sub_batch) {
+            const uint64_t sb = std::min(p->sub_batch, frames - s0);
+            const uint64_t ta = sb * (p->n2 / (uint64_t)cd->cols);
+            const uint64_t tb = sb * (p->n1 / (uint64_t)rd->rows);
+            const unsigned ga = grid_for(cd->kernel_frames[dir > 0], cd->threads * cd->cols, ta,
+                                         p->device, p->grid_mult);
+            const unsigned gb = grid_for(rd->kernel[dir > 0], rd->threads * rd->rows, tb,
+                                         p->device, p->grid_mult);
+            cd->launch_frames(dir, in + s0 * hop, p->scratch, p->tw, p->tl, p->th, p->sh,
+                              (int)p->n2, sb, hop, window, ga, s);
+            rd->launch(dir, p->scratch, out + s0 * n, p->tw2, (int)p->n1, sb, gb, s);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return hip_error(e, "frame kernel launch");
+        p->used = true;
+        p->last_stream = s;
+        p->last_stream_valid = true;
+        return set_ok();
     }
     const uint64_t total = frames * n;
     const unsigned grid = (unsigned)std::min<uint64_t>((total + 255) / 256, 1u << 20);

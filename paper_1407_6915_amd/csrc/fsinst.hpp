@@ -12,9 +12,10 @@ namespace fs {
 // stages, or all but the last); XCD-aware tile order; register allocation
 // for 2 waves per SIMD; lane index kept across the tiles of the persistent
 // loop; split (real, then imaginary) LDS exchanges; register allocation for
-// 4 / 8 waves per SIMD
+// 4 / 8 waves per SIMD; the column pass also comes in a form that reads
+// overlapping, windowed frames (one row per length)
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
-              kSplit = 64, kW4 = 128, kW8 = 256;
+              kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -53,6 +54,20 @@ struct ColInst {
                                (const c32 *)in, (c32 *)ybuf, (const c32 *)tw,
                                (const c32 *)tl, (const c32 *)th, sh, n2, batch);
     }
+    static void launch_frames(int dir, const void *in, void *ybuf, const void *tw,
+                              const void *tl, const void *th, int sh, int n2, uint64_t batch,
+                              uint64_t hop, const float *window, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_columns_frames_kernel<Sh, Pol, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, hop, window);
+        else
+            hipLaunchKernelGGL((four_step_columns_frames_kernel<Sh, Pol, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, hop, window);
+    }
     static ColumnDesc desc(int variant)
     {
         ColumnDesc d{};
@@ -69,6 +84,11 @@ struct ColInst {
         d.launch = &launch;
         d.kernel[0] = (const void *)&four_step_columns_kernel<Sh, Pol, -1>;
         d.kernel[1] = (const void *)&four_step_columns_kernel<Sh, Pol, 1>;
+        if constexpr ((F & kFrames) != 0) {
+            d.launch_frames = &launch_frames;
+            d.kernel_frames[0] = (const void *)&four_step_columns_frames_kernel<Sh, Pol, -1>;
+            d.kernel_frames[1] = (const void *)&four_step_columns_frames_kernel<Sh, Pol, 1>;
+        }
         return d;
     }
 };

@@ -21,6 +21,10 @@ using col_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *
                                uint64_t batch, unsigned grid, hipStream_t s);
 using row_launch_fn = void (*)(int dir, const void *ybuf, void *out, const void *tw,
                                int n1, uint64_t batch, unsigned grid, hipStream_t s);
+using col_frames_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
+                                      const void *tl, const void *th, int sh, int n2,
+                                      uint64_t batch, uint64_t hop, const float *window,
+                                      unsigned grid, hipStream_t s);
 
 // One LDS-resident pass over whole segments.
 struct SinglePassDesc {
@@ -50,6 +54,8 @@ struct ColumnDesc {
     int radices[kMaxRadices];
     col_launch_fn launch;
     const void *kernel[2];
+    col_frames_launch_fn launch_frames;  // overlapping/windowed frames as input
+    const void *kernel_frames[2];
 };
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.

@@ -933,6 +933,52 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     }
 }
 
+// Pass A over overlapping, windowed frames (short-time transform): frame s
+// starts at in + s * hop and its sample n is multiplied by window[n] (window
+// may be null) as the column loads read it; otherwise as
+// four_step_columns_kernel.  Y keeps one N1 x N2 block per frame.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    four_step_columns_frames_kernel(const c32 *in, c32 *ybuf, const c32 *__restrict__ tw,
+                                    const c32 *__restrict__ tl, const c32 *__restrict__ th,
+                                    int sh, int n2, uint64_t batch, uint64_t hop,
+                                    const float *__restrict__ window)
+{
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
+    using S0 = Stage<Sh, 0, 1>;
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
+    const uint64_t blocks = (uint64_t)(n2 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
+        const uint64_t seg = g / blocks;
+        const int first = (int)(g - seg * blocks) * Pol::C;
+        const int tid = Pol::kPlainLane ? (int)threadIdx.x : opaque_lane();
+        const int c = Pol::template col<0>(tid);
+        const int t = Pol::template thr<0>(tid);
+        const FourStepCtx ctx{nullptr, ybuf + seg * nseg, first, Sh::M, n2, tl, th, sh, true};
+        c32 v[Sh::kMaxE];
+        const c32 *xc = in + seg * hop + first + c;
+        if (window) {
+            const float *wc = window + first + c;
+            st_gather<S0, Sh>(v, t, [&](int i) {
+                const c32 a = gload<Pol::kNT>(xc + (size_t)i * n2);
+                const float w = wc[(size_t)i * n2];
+                return c32{a.x * w, a.y * w};
+            });
+        } else {
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
+        }
+        if constexpr (Pol::kSplit)
+            tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid,
+                                             threadIdx.x, ctx);
+        else
+            tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, threadIdx.x, ctx);
+    }
+}
+
 // Pass B: lanes row-major (c = tid / T, t = tid % T) up to the last stage,
 // row-fastest (c = tid % C, t = tid / C) in the last stage so the
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.

@@ -1,6 +1,7 @@
 """Overlapping, windowed segments (fft_exec_frames) against the FP64
 oracle's short-time transform, on every plan kind: one-pass lengths read
-the frames in the kernel, two-pass and fallback lengths gather first."""
+the frames in the kernel, two-pass lengths in their column pass, radix-stage
+lengths gather first."""
 import numpy as np
 import pytest
 
@@ -35,7 +36,9 @@ def run_frames(n, x, hop, n_frames, window, direction=fs.FORWARD, batch=None):
     (4096, 4099, 5),        # gaps between frames
     (1000, 333, 17),        # non power of two, odd hop
     (16384, 8192, 7),
-    (1 << 16, 1 << 14, 5),  # two-pass length: gathered, then in place
+    (1 << 16, 1 << 14, 5),  # two-pass lengths: read by the column pass
+    (1 << 15, 1000, 6),
+    (1 << 18, 70001, 4),
     (3 ** 9, 5000, 4),      # radix-stage fallback
     (1, 1, 11),             # identity length
 ])
@@ -122,3 +125,24 @@ def test_frames_argument_errors():
                 f()
             assert e.value.name == name
     torch.cuda.synchronize()
+
+
+def test_two_pass_frames_across_sub_batches():
+    """2^20-point frames, more of them than one scratch sub-batch holds
+    (512): frames on both sides of the boundary against the oracle."""
+    import torch
+    n, hop, frames = 1 << 20, 4099, 513
+    announce("frames n=%d hop=%d frames=%d" % (n, hop, frames))
+    total = (frames - 1) * hop + n
+    x = siggen.Signal(seed=45, seg_len=1, sigma=1.0).samples(0, total)
+    w = hann32(n)
+    xd = torch.from_numpy(x).to("cuda")
+    wd = torch.from_numpy(w).to("cuda")
+    with fs.Plan(n, frames) as p:
+        assert p.describe()["sub_batch"] == 512
+        y = p.exec_frames(xd, hop, frames, wd)
+    torch.cuda.synchronize()
+    for f in (0, 1, 511, 512):
+        got = y[f * n:(f + 1) * n].cpu().numpy()[None]
+        ref = oracle.short_time(x[f * hop:f * hop + n], n, hop, 1, w)
+        assert oracle.rel_l2(got, ref)[0] <= oracle.tolerance(n), f
