@@ -358,13 +358,32 @@ def frames(args):
         t_plain = _time(torch, lambda: p.exec_ptr(x.data_ptr(), y.data_ptr(), sh, seg),
                         args.steps)
     out_bytes = nf * n * 8
+    # 65536-point frames every 16384 samples: read by the two-pass plan's
+    # column pass (75 % overlap, Hann), next to as many disjoint segments
+    n2, hop2 = 1 << 16, 1 << 14
+    nf2 = (total - n2) // hop2 + 1
+    j2 = torch.arange(n2, dtype=torch.float64, device="cuda")
+    w2 = (0.5 - 0.5 * torch.cos(2 * math.pi * j2 / n2)).float()
+    y2 = torch.empty(nf2 * n2, dtype=torch.complex64, device="cuda")
+    with fs.Plan(n2, nf2) as p:
+        t2 = _time(torch, lambda: p.exec_frames_ptr(x.data_ptr(), total, y2.data_ptr(), nf2,
+                                                    hop2, w2.data_ptr(), sh), args.steps)
+        seg2 = total // n2
+        t2p = _time(torch, lambda: p.exec_ptr(x.data_ptr(), y2.data_ptr(), sh, seg2),
+                    args.steps)
+    del y2
+    two_pass = {"segment_len": n2, "hop": hop2, "frames": nf2, "ms": round(t2 * 1e3, 3),
+                "frame_bytes_two_pass_GBps": round(32.0 * nf2 * n2 / t2 / 1e9, 1),
+                "plain_segments_ms": round(t2p * 1e3, 3),
+                "plain_two_pass_GBps": round(32.0 * seg2 * n2 / t2p / 1e9, 1)}
     print(json.dumps({"workload": "frames_n4096_hop1024_hann", "segment_len": n, "hop": hop,
                       "frames": nf, "signal_samples": total, "ms": round(t * 1e3, 3),
                       "GFLOP/s": round(FLOP(n) * nf / t / 1e9, 1),
                       "frame_bytes_GBps": round(2 * out_bytes / t / 1e9, 1),
                       "min_hbm_bytes_GBps": round((total * 8 + out_bytes) / t / 1e9, 1),
                       "plain_segments_ms": round(t_plain * 1e3, 3),
-                      "plain_GBps": round(16.0 * seg * n / t_plain / 1e9, 1)}), flush=True)
+                      "plain_GBps": round(16.0 * seg * n / t_plain / 1e9, 1),
+                      "two_pass_n65536_hop16384": two_pass}), flush=True)
     return 0
 
 
