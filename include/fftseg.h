@@ -315,8 +315,9 @@ int fft_exec_segments_graph(fft_plan_t plan, const void *in, void *out, void *st
  * threads per segment, segments per workgroup, LDS padding, streamed or
  * cached global access) at persistent-grid sizes {0, 4, 8, 16, 32, 64}
  * resident workgroup waves per CU (two-pass lengths: every column-tile x
- * row-tile variant of the chosen split, columns/rows per workgroup, tile
- * order, streamed access, at each grid size), on
+ * row-tile variant of the planner's split n1 x n2, columns/rows per
+ * workgroup, tile order, streamed access, and the default tiles of every
+ * other split n1' x n/n1' with compiled tiles, at each grid size), on
  * device buffers of batch segments it allocates and frees.  The fastest
  * choice goes into the process-wide tuning table used by later plans and,
  * if path != NULL, is merged into that JSON cache file.  Returns the number
@@ -326,8 +327,8 @@ int fft_autotune(size_t segment_len, size_t batch, int direction, const char *pa
                  double *best_us);
 
 /* Load a cache written by fft_autotune for this device's architecture;
- * entries naming variants this build lacks are skipped.  Returns the number
- * of entries loaded. */
+ * entries naming variants or splits this build lacks are skipped.  Returns
+ * the number of entries loaded. */
 int fft_tune_load(const char *path);
 
 /* Forget every tuned choice (plans use the built-in defaults again). */

@@ -157,13 +157,14 @@ int tuned_grid_mult(uint64_t n, int variant, int fallback)
     return fallback;
 }
 
-void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant)
+void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant, uint64_t *n1)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &p : g_tuned)
         if (p.n == n && p.variant < 0) {
             *col_variant = p.col_variant;
             *row_variant = p.row_variant;
+            *n1 = p.n1;
             return;
         }
 }
@@ -225,7 +226,7 @@ int variant_count(uint64_t n)
 // the split is chosen on the default tiles, then the requested variants of
 // those lengths are used (default where a variant does not exist)
 bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,
-                int row_variant)
+                int row_variant, uint64_t want_n1)
 {
     int nc = 0, nr = 0;
     const ColumnDesc *ct = column_table(&nc);
@@ -234,7 +235,8 @@ bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col
     *col = nullptr;
     *row = nullptr;
     for (int i = 0; i < nc; ++i) {
-        if (ct[i].variant != 0 || n % (uint64_t)ct[i].n1)
+        if (ct[i].variant != 0 || n % (uint64_t)ct[i].n1 ||
+            (want_n1 && (uint64_t)ct[i].n1 != want_n1))
             continue;
         const uint64_t n2 = n / (uint64_t)ct[i].n1;
         for (int j = 0; j < nr; ++j) {
@@ -264,6 +266,21 @@ bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col
         if ((uint64_t)rt[j].n2 == n2 && rt[j].variant == row_variant && fits(**col, rt[j]))
             *row = &rt[j];
     return fits(**col, **row);
+}
+
+std::vector<uint64_t> split_candidates(uint64_t n)
+{
+    std::vector<uint64_t> out;
+    int nc = 0;
+    const ColumnDesc *ct = column_table(&nc);
+    for (int i = 0; i < nc; ++i) {
+        const ColumnDesc *c = nullptr;
+        const RowDesc *r = nullptr;
+        if (ct[i].variant == 0 && n % (uint64_t)ct[i].n1 == 0 &&
+            find_split(n, &c, &r, 0, 0, (uint64_t)ct[i].n1))
+            out.push_back((uint64_t)ct[i].n1);
+    }
+    return out;
 }
 
 int split_variant_counts(uint64_t n, int *ncol, int *nrow)
@@ -354,7 +371,7 @@ int env_grid_mult()
 // ---------------------------------------------------------------------------
 // plan construction
 int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
-               int forced_split_variants)
+               int forced_split_variants, uint64_t forced_n1)
 {
     p->n = n;
     p->batch = batch;
@@ -404,13 +421,20 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
     if (!getenv("FFTSEG_GRID_MULT"))
         p->grid_mult = tuned_grid_mult(n, -1, kTwoPassGridMult);
     int cv = 0, rv = 0;
+    uint64_t n1 = forced_n1;
     if (forced_split_variants >= 0) {
         cv = forced_split_variants & 0xff;
         rv = (forced_split_variants >> 8) & 0xff;
-    } else {
-        tuned_split_variants(n, &cv, &rv);
+    } else if (!forced_n1) {
+        tuned_split_variants(n, &cv, &rv, &n1);
     }
-    if (find_split(n, &p->col, &p->row, cv, rv)) {
+    bool split = find_split(n, &p->col, &p->row, cv, rv, n1);
+    if (!split && n1 && !forced_n1)
+        split = find_split(n, &p->col, &p->row, 0, 0, 0);  // a tuned split this build lacks
+    if (!split && forced_n1)
+        return set_error(FFT_ERR_INVALID_ARG, "length %llu has no split with %llu columns",
+                         (unsigned long long)n, (unsigned long long)forced_n1);
+    if (split) {
         p->kind = Plan::FOURSTEP;
         p->n1 = (uint64_t)p->col->n1;
         p->n2 = (uint64_t)p->row->n2;

@@ -60,8 +60,11 @@ c32 root_forward(uint64_t m, uint64_t n);
 const SinglePassDesc *find_single(uint64_t n, int variant);
 const SinglePassDesc *find_aux(uint64_t n);
 int variant_count(uint64_t n);
+// n1: the column length to use (0: the planner's balanced choice)
 bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,
-                int row_variant);
+                int row_variant, uint64_t n1 = 0);
+// every column length n1 for which n = n1 * n2 has compiled column and row tiles
+std::vector<uint64_t> split_candidates(uint64_t n);
 int split_variant_counts(uint64_t n, int *ncol, int *nrow);
 unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
                   int grid_mult);
@@ -69,8 +72,9 @@ unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev
 int validate_create(uint64_t n, uint64_t batch, int dir);
 // forced_variant: single-pass variant (-1: tuned/default); forced_split_variants:
 // column variant | row variant << 8 of a four-step plan (-1: tuned/default)
+// forced_n1: column length of a four-step plan (0: tuned/default)
 int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
-               int forced_split_variants = -1);
+               int forced_split_variants = -1, uint64_t forced_n1 = 0);
 void plan_free(Plan *p);
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
 // real-input plans: length n = 2m through the m-point one-pass kernel, or,
@@ -94,10 +98,11 @@ struct TunedChoice {
     uint64_t batch;
     int col_variant;  // two-pass plans: column and row tile variants
     int row_variant;
+    uint64_t n1 = 0;  // two-pass plans: column length of the split (0: the planner's)
 };
 int tuned_variant(uint64_t n);
 int tuned_grid_mult(uint64_t n, int variant, int fallback);
-void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant);
+void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant, uint64_t *n1);
 void set_tuned(const TunedChoice &c);
 void clear_tuned();
 std::vector<TunedChoice> tuned_snapshot();

@@ -131,7 +131,7 @@ int write_cache(const char *path)
     const std::string arch = arch_name();
     if (read_file(path, old) && arch_of(old) == arch) {
         for (const std::string &o : entry_objects(old)) {
-            double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0;
+            double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0, n1 = 0;
             if (!read_number(o, "n", &n) || !read_number(o, "variant", &v) ||
                 !read_number(o, "grid_mult", &g))
                 continue;
@@ -139,11 +139,13 @@ int write_cache(const char *path)
             read_number(o, "batch", &b);
             read_number(o, "column_variant", &cv);
             read_number(o, "row_variant", &rv);
+            read_number(o, "n1", &n1);
             bool have = false;
             for (auto &m : merged)
                 have |= m.n == (uint64_t)n;
             if (!have)
-                merged.push_back({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv});
+                merged.push_back({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
+                                  (uint64_t)n1});
         }
     }
     std::sort(merged.begin(), merged.end(),
@@ -156,10 +158,12 @@ int write_cache(const char *path)
     for (size_t i = 0; i < merged.size(); ++i)
         fprintf(f,
                 "    {\"n\": %llu, \"variant\": %d, \"grid_mult\": %d, \"us\": %.3f, "
-                "\"batch\": %llu, \"column_variant\": %d, \"row_variant\": %d}%s\n",
+                "\"batch\": %llu, \"column_variant\": %d, \"row_variant\": %d, "
+                "\"n1\": %llu}%s\n",
                 (unsigned long long)merged[i].n, merged[i].variant, merged[i].grid_mult,
                 merged[i].us, (unsigned long long)merged[i].batch, merged[i].col_variant,
-                merged[i].row_variant, i + 1 < merged.size() ? "," : "");
+                merged[i].row_variant, (unsigned long long)merged[i].n1,
+                i + 1 < merged.size() ? "," : "");
     fprintf(f, "  ]\n}\n");
     fclose(f);
     if (rename(tmp.c_str(), path) != 0)
@@ -198,17 +202,30 @@ extern "C" int fft_autotune(size_t segment_len, size_t batch, int direction, con
         int ncol = 0, nrow = 0;
         if (nv == 0)
             split_variant_counts(segment_len, &ncol, &nrow);
-        // candidate (single-pass variant | column variant, row variant)
-        std::vector<std::pair<int, int>> cand;
-        if (nv > 0)
+        // candidates: single-pass variants; or, for two-pass lengths, every
+        // column x row tile variant of the planner's split and the default
+        // tiles of every other split n1 x n/n1 with compiled tiles
+        struct Cand {
+            int first, second;
+            uint64_t n1;  // 0: the planner's split
+        };
+        std::vector<Cand> cand;
+        if (nv > 0) {
             for (int v = 0; v < nv; ++v)
-                cand.push_back({v, -1});
-        else if (ncol > 0)
+                cand.push_back({v, -1, 0});
+        } else if (ncol > 0) {
             for (int c = 0; c < ncol; ++c)
                 for (int r = 0; r < nrow; ++r)
-                    cand.push_back({c, r});
-        else
-            cand.push_back({-1, -1});
+                    cand.push_back({c, r, 0});
+            const ColumnDesc *dc = nullptr;
+            const RowDesc *dr = nullptr;
+            find_split(segment_len, &dc, &dr, 0, 0);
+            for (uint64_t n1 : split_candidates(segment_len))
+                if (n1 != (uint64_t)dc->n1)
+                    cand.push_back({0, 0, n1});
+        } else {
+            cand.push_back({-1, -1, 0});
+        }
         double best = 1e300;
         TunedChoice choice{segment_len, nv > 0 ? 0 : -1, 0, 0, batch, 0, 0};
         int timed = 0, st = FFT_OK;
@@ -221,12 +238,13 @@ extern "C" int fft_autotune(size_t segment_len, size_t batch, int direction, con
                     st = plan_build(&p, segment_len, batch, direction, cv.first, -1);
                 else
                     st = plan_build(&p, segment_len, batch, direction, -1,
-                                    ncol > 0 ? (cv.first | (cv.second << 8)) : -1);
+                                    ncol > 0 ? (cv.first | (cv.second << 8)) : -1, cv.n1);
                 if (st != FFT_OK) {
                     plan_free(&p);
                     break;
                 }
                 p.grid_mult = m;
+                const uint64_t plan_n1 = p.kind == Plan::FOURSTEP ? p.n1 : 0;
                 double us = 0;
                 st = time_plan(&p, in, out, s, 5, &us);
                 plan_free(&p);
@@ -238,6 +256,7 @@ extern "C" int fft_autotune(size_t segment_len, size_t batch, int direction, con
                     choice.variant = nv > 0 ? cv.first : -1;
                     choice.col_variant = nv > 0 ? 0 : std::max(cv.first, 0);
                     choice.row_variant = nv > 0 ? 0 : std::max(cv.second, 0);
+                    choice.n1 = plan_n1;
                     choice.grid_mult = m;
                     choice.us = us;
                 }
@@ -276,21 +295,26 @@ extern "C" int fft_tune_load(const char *path)
                              mine.c_str());
         int k = 0;
         for (const std::string &o : entry_objects(js)) {
-            double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0;
+            double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0, n1 = 0;
             if (!read_number(o, "n", &n) || !read_number(o, "variant", &v) ||
                 !read_number(o, "grid_mult", &g))
                 continue;
             read_number(o, "column_variant", &cv);
             read_number(o, "row_variant", &rv);
+            read_number(o, "n1", &n1);
             int ncol = 0, nrow = 0;
             if (v < 0)
                 split_variant_counts((uint64_t)n, &ncol, &nrow);
+            const ColumnDesc *sc = nullptr;
+            const RowDesc *sr = nullptr;
             if (n < 1 || (v >= 0 && v >= variant_count((uint64_t)n)) || g < 0 || g > 1024 ||
-                (v < 0 && (cv < 0 || rv < 0 || (ncol && cv >= ncol) || (nrow && rv >= nrow))))
+                (v < 0 && (cv < 0 || rv < 0 || (ncol && cv >= ncol) || (nrow && rv >= nrow))) ||
+                n1 < 0 || (n1 > 0 && !find_split((uint64_t)n, &sc, &sr, 0, 0, (uint64_t)n1)))
                 continue;  // stale entry for variants this build does not have
             read_number(o, "us", &us);
             read_number(o, "batch", &b);
-            set_tuned({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv});
+            set_tuned({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
+                       (uint64_t)n1});
             ++k;
         }
         set_ok();

@@ -58,13 +58,18 @@ def test_autotune_and_cache(tmp_path):
     with fs.Plan(4096, 64) as p:
         y = p.exec(xd).cpu().numpy().reshape(64, 4096)
     assert np.all(oracle.rel_l2(y, oracle.fft_recursive(x, 4096)) <= oracle.tolerance(4096))
-    # two-pass lengths tune tile variants x grid; merged into the same file
+    # two-pass lengths tune tile variants x grid and the split itself (the
+    # planner's 256 x 256 and the other splits with tiles: 128 x 512,
+    # 512 x 128); merged into the same file
+    n1, n2, nc, nr = fs.split_info(1 << 16)
     k2, _ = fs.autotune(1 << 16, 64, fs.FORWARD, path)
-    assert k2 >= 6 and k2 % 6 == 0
+    assert k2 == 6 * (nc * nr + 2)
     js = json.load(open(path))
     assert {e["n"] for e in js["entries"]} == {4096, 1 << 16}
     e2 = [e for e in js["entries"] if e["n"] == 1 << 16][0]
+    assert e2["n1"] in (128, 256, 512)
     d2 = fs.Plan(1 << 16, 4).describe()
+    assert d2["n1"] == e2["n1"] and d2["n1"] * d2["n2"] == 1 << 16
     assert d2["column_variant"] == e2["column_variant"]
     assert d2["row_variant"] == e2["row_variant"] and d2["grid_mult"] == e2["grid_mult"]
     x2 = noise(1 << 16, 4, seed=3)
