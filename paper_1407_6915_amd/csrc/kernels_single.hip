@@ -35,11 +35,13 @@ const SinglePassDesc kTable[] = {
     SpInst<1024, 64, 4, 4, kPlain, 16, 16, 4>::desc(2, 32),
     SpInst<1024, 64, 4, 4, kNT, 16, 16, 4>::desc(3, 32),
     SpInst<1024, 64, 4, 4, kClassic, 16, 16, 4>::desc(4, 32),
+    pad32_desc(1, 5, 64),
     SpInst<2048, 128, 1, 4, kNT | kPlain | kAux, 16, 16, 8>::desc(0, 64),
     SpInst<2048, 128, 2, 4, kNT | kPlain, 16, 16, 8>::desc(1, 64),
     SpInst<2048, 128, 2, 4, kPlain, 16, 16, 8>::desc(2, 32),
     SpInst<2048, 128, 2, 4, kClassic, 16, 16, 8>::desc(3, 32),
-    SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 64),
+    pad32_desc(3, 4, 64),
+    SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 32),
     SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
     // (variant 3 first: the length's frame and real-input kernels are the
     // first row with them)
@@ -54,12 +56,14 @@ const SinglePassDesc kTable[] = {
     shuffle4096_desc(10, 32, 2),
     SpInst<4096, 256, 1, 0, kPrefetch | kNT, 16, 16, 16>::desc(11, 32),
     SpInst<4096, 512, 1, 4, kPrefetch | kNT, 8, 8, 8, 8>::desc(12, 32),
-    SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(0, 16),
+    pad32_desc(0, 13, 64),
+    pad32_desc(2, 0, 16),
     SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(1, 32),
     SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(2, 32),
     SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(3, 32),
     SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(4, 32),
     SpInst<8192, 512, 1, 4, kPrefetch | kNT, 16, 16, 16, 2>::desc(5, 32),
+    SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(6, 16),
     split_desc(0, 0, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(1, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),

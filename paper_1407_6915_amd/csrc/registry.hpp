@@ -74,6 +74,8 @@ SinglePassDesc shuffle4096_desc(int variant, int grid_mult, int nontemporal);
 SinglePassDesc split_desc(int config, int variant, int grid_mult);
 ColumnDesc split_column_desc(int config, int variant);
 RowDesc split_row_desc(int config, int variant);
+// single-pass instances with one LDS pad element every 32 (kernels_pad.hip)
+SinglePassDesc pad32_desc(int config, int variant, int grid_mult);
 // four-step tiles with radix-32 stages (kernels_radix32.hip)
 ColumnDesc radix32_column_desc(int config, int variant);
 RowDesc radix32_row_desc(int config, int variant);
