@@ -113,7 +113,9 @@ fft_plan_t fft_plan_create_real(size_t segment_len, size_t batch, int direction)
  * `in` yields its spectrum at the same offset of `out`.  in == out (in
  * place) is allowed; any other overlap gives FFT_ERR_OVERLAP.  Each buffer
  * must lie inside one device allocation of at least batch*segment_len*8
- * bytes from the pointer on (else FFT_ERR_BOUNDS). */
+ * bytes from the pointer on (else FFT_ERR_BOUNDS).  Pointers need 8-byte
+ * alignment only; two-pass plans start their tiles where the buffers'
+ * 128-byte lines do, so bases off a line boundary cost them little. */
 int fft_exec_segments(fft_plan_t plan, const void *in, void *out, void *stream);
 
 /* Same as fft_exec_segments for the first `batch` segments only

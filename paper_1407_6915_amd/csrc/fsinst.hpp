@@ -13,9 +13,11 @@ namespace fs {
 // for 2 waves per SIMD; lane index kept across the tiles of the persistent
 // loop; split (real, then imaginary) LDS exchanges; register allocation for
 // 4 / 8 waves per SIMD; the column pass also comes in a form that reads
-// overlapping, windowed frames (one row per length)
+// overlapping, windowed frames; both passes also come in a form whose blocks
+// start at any column / row and wrap round (for segments off a line
+// boundary); one row per length carries each of these forms
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
-              kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024;
+              kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -40,6 +42,23 @@ struct ColInst {
     using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                              (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
                              (F & kSplit) != 0>;
+    using PolW = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                              (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
+                              (F & kSplit) != 0, true>;
+    static void launch_shifted(int dir, const void *in, void *ybuf, const void *tw,
+                               const void *tl, const void *th, int sh, int n2, uint64_t batch,
+                               int shift, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_columns_shifted_kernel<Sh, PolW, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, shift);
+        else
+            hipLaunchKernelGGL((four_step_columns_shifted_kernel<Sh, PolW, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, shift);
+    }
     static void launch(int dir, const void *in, void *ybuf, const void *tw,
                        const void *tl, const void *th, int sh, int n2,
                        uint64_t batch, unsigned grid, hipStream_t s)
@@ -89,6 +108,11 @@ struct ColInst {
             d.kernel_frames[0] = (const void *)&four_step_columns_frames_kernel<Sh, Pol, -1>;
             d.kernel_frames[1] = (const void *)&four_step_columns_frames_kernel<Sh, Pol, 1>;
         }
+        if constexpr ((F & kShifted) != 0) {
+            d.launch_shifted = &launch_shifted;
+            d.kernel_shifted[0] = (const void *)&four_step_columns_shifted_kernel<Sh, PolW, -1>;
+            d.kernel_shifted[1] = (const void *)&four_step_columns_shifted_kernel<Sh, PolW, 1>;
+        }
         return d;
     }
 };
@@ -99,6 +123,20 @@ struct RowInst {
     using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                           (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
                           (F & kSplit) != 0>;
+    using PolW = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                           (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
+                           (F & kSplit) != 0, true>;
+    static void launch_shifted(int dir, const void *ybuf, void *out, const void *tw, int n1,
+                               uint64_t batch, int shift, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_rows_shifted_kernel<Sh, PolW, -1>), g, b, 0, s,
+                               (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch, shift);
+        else
+            hipLaunchKernelGGL((four_step_rows_shifted_kernel<Sh, PolW, 1>), g, b, 0, s,
+                               (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch, shift);
+    }
     static void launch(int dir, const void *ybuf, void *out, const void *tw, int n1,
                        uint64_t batch, unsigned grid, hipStream_t s)
     {
@@ -126,6 +164,11 @@ struct RowInst {
         d.launch = &launch;
         d.kernel[0] = (const void *)&four_step_rows_kernel<Sh, Pol, -1>;
         d.kernel[1] = (const void *)&four_step_rows_kernel<Sh, Pol, 1>;
+        if constexpr ((F & kShifted) != 0) {
+            d.launch_shifted = &launch_shifted;
+            d.kernel_shifted[0] = (const void *)&four_step_rows_shifted_kernel<Sh, PolW, -1>;
+            d.kernel_shifted[1] = (const void *)&four_step_rows_shifted_kernel<Sh, PolW, 1>;
+        }
         return d;
     }
 };

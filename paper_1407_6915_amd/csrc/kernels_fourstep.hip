@@ -10,10 +10,10 @@ using namespace fs;
 // Variant 0 of each length is the default; the tuner tries the others.
 //                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
-    ColInst<128, 8, 16, 4, kFrames, 16, 8>::desc(0),
+    ColInst<128, 8, 16, 4, kFrames | kShifted, 16, 8>::desc(0),
     ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     ColInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames, 16, 16>::desc(0),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames | kShifted, 16, 16>::desc(0),
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
@@ -39,17 +39,17 @@ const ColumnDesc kColumns[] = {
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(10),
     split_column_desc(0, 11),
     split_column_desc(2, 12),
-    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames, 16, 16, 8>::desc(0),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames | kShifted, 16, 16, 8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(1),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(2),
     split_column_desc(1, 3),
 };
 
 const RowDesc kRows[] = {
-    RowInst<128, 8, 16, 4, 0, 16, 8>::desc(0),
+    RowInst<128, 8, 16, 4, kShifted, 16, 8>::desc(0),
     RowInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     RowInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(0),
+    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kShifted, 16, 16>::desc(0),
     RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
@@ -75,7 +75,7 @@ const RowDesc kRows[] = {
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(10),
     split_row_desc(0, 11),
     split_row_desc(2, 12),
-    RowInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(0),
+    RowInst<2048, 128, 8, 4, kNoHoist | kShifted, 16, 16, 8>::desc(0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),
     split_row_desc(1, 3),

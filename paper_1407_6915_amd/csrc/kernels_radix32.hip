@@ -14,9 +14,11 @@ ColumnDesc radix32_column_desc(int config, int variant)
     //                        M     T   C  PS  F                        radices
     switch (config) {
     case 0:
-        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kFrames, 32, 32>::desc(variant);
+        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kFrames | kShifted, 32, 32>::desc(
+            variant);
     case 1:
-        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kFrames, 32, 16>::desc(variant);
+        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kFrames | kShifted, 32, 16>::desc(
+            variant);
     case 2:
         return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     default:
@@ -29,9 +31,9 @@ RowDesc radix32_row_desc(int config, int variant)
     using namespace fs;
     switch (config) {
     case 0:
-        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kShifted, 32, 32>::desc(variant);
     case 1:
-        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
+        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kShifted, 32, 16>::desc(variant);
     case 2:
         return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     default:

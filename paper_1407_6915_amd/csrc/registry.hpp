@@ -21,6 +21,12 @@ using col_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *
                                uint64_t batch, unsigned grid, hipStream_t s);
 using row_launch_fn = void (*)(int dir, const void *ybuf, void *out, const void *tw,
                                int n1, uint64_t batch, unsigned grid, hipStream_t s);
+using col_shifted_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
+                                       const void *tl, const void *th, int sh, int n2,
+                                       uint64_t batch, int shift, unsigned grid, hipStream_t s);
+using row_shifted_launch_fn = void (*)(int dir, const void *ybuf, void *out, const void *tw,
+                                       int n1, uint64_t batch, int shift, unsigned grid,
+                                       hipStream_t s);
 using col_frames_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
                                       const void *tl, const void *th, int sh, int n2,
                                       uint64_t batch, uint64_t hop, const float *window,
@@ -56,6 +62,8 @@ struct ColumnDesc {
     const void *kernel[2];
     col_frames_launch_fn launch_frames;  // overlapping/windowed frames as input
     const void *kernel_frames[2];
+    col_shifted_launch_fn launch_shifted;  // blocks from a column offset, wrapping
+    const void *kernel_shifted[2];
 };
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.
@@ -64,6 +72,8 @@ struct RowDesc {
     int radices[kMaxRadices];
     row_launch_fn launch;
     const void *kernel[2];
+    row_shifted_launch_fn launch_shifted;  // blocks from a row offset, wrapping
+    const void *kernel_shifted[2];
 };
 
 const SinglePassDesc *single_pass_table(int *count);

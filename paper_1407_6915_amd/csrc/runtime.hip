@@ -283,6 +283,26 @@ std::vector<uint64_t> split_candidates(uint64_t n)
     return out;
 }
 
+const ColumnDesc *find_column_shifted(uint64_t n1)
+{
+    int nc = 0;
+    const ColumnDesc *ct = column_table(&nc);
+    for (int i = 0; i < nc; ++i)
+        if ((uint64_t)ct[i].n1 == n1 && ct[i].launch_shifted)
+            return &ct[i];
+    return nullptr;
+}
+
+const RowDesc *find_row_shifted(uint64_t n2)
+{
+    int nr = 0;
+    const RowDesc *rt = row_table(&nr);
+    for (int j = 0; j < nr; ++j)
+        if ((uint64_t)rt[j].n2 == n2 && rt[j].launch_shifted)
+            return &rt[j];
+    return nullptr;
+}
+
 int split_variant_counts(uint64_t n, int *ncol, int *nrow)
 {
     const ColumnDesc *c = nullptr;
@@ -442,7 +462,8 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
             (e = upload(root_table(p->n2), &p->tw2)) != hipSuccess)
             return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
                                             : hip_error(e, "twiddle upload");
-        p->scratch_bytes = p->sub_batch * n * sizeof(c32);
+        // (one line more: Y may start at the input's offset within a line)
+        p->scratch_bytes = (p->sub_batch * n + kLineSamples) * sizeof(c32);
     } else {
         p->kind = Plan::GENERIC;
         p->radices = generic_radices(n);
@@ -686,6 +707,39 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
     case Plan::FOURSTEP: {
         const ColumnDesc *cd = p->col;
         const RowDesc *rd = p->row;
+        // Segments that start inside a 128-byte line (a base pointer off a
+        // line boundary): column blocks start at the first line-aligned
+        // column and wrap round, Y sits at the input's offset within a
+        // line, and row blocks start where the output's lines do, so both
+        // passes move whole lines.  The shifted forms exist for each
+        // length's default tiles.
+        const uint64_t in_m = ((uintptr_t)in / sizeof(c32)) % kLineSamples,
+                       out_m = ((uintptr_t)out / sizeof(c32)) % kLineSamples;
+        if (in_m || out_m) {
+            const ColumnDesc *cs = cd->launch_shifted ? cd : find_column_shifted(p->n1);
+            const RowDesc *rs = rd->launch_shifted ? rd : find_row_shifted(p->n2);
+            if (cs && rs && p->n2 % (uint64_t)cs->cols == 0 && p->n1 % (uint64_t)rs->rows == 0) {
+                const int sa = (int)((kLineSamples - in_m) % kLineSamples);
+                const int sb = (int)((kLineSamples - out_m) % kLineSamples);
+                c32 *ybuf = (c32 *)p->scratch + in_m;
+                for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch) {
+                    const uint64_t sbat = std::min(p->sub_batch, batch - s0);
+                    const uint64_t ta = sbat * (p->n2 / (uint64_t)cs->cols);
+                    const uint64_t tb = sbat * (p->n1 / (uint64_t)rs->rows);
+                    const unsigned ga = grid_for(cs->kernel_shifted[dir > 0],
+                                                 cs->threads * cs->cols, ta, p->device,
+                                                 p->grid_mult);
+                    const unsigned gb = grid_for(rs->kernel_shifted[dir > 0],
+                                                 rs->threads * rs->rows, tb, p->device,
+                                                 p->grid_mult);
+                    cs->launch_shifted(dir, (const c32 *)in + s0 * n, ybuf, p->tw, p->tl, p->th,
+                                       p->sh, (int)p->n2, sbat, sa, ga, s);
+                    rs->launch_shifted(dir, ybuf, (c32 *)out + s0 * n, p->tw2, (int)p->n1, sbat,
+                                       sb, gb, s);
+                }
+                break;
+            }
+        }
         for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch) {
             const uint64_t sb = std::min(p->sub_batch, batch - s0);
             const c32 *x = (const c32 *)in + s0 * n;

@@ -65,6 +65,12 @@ bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col
                 int row_variant, uint64_t n1 = 0);
 // every column length n1 for which n = n1 * n2 has compiled column and row tiles
 std::vector<uint64_t> split_candidates(uint64_t n);
+// the column / row tiles of a length that have the shifted (line-aligned,
+// wrapping) form, or null
+const ColumnDesc *find_column_shifted(uint64_t n1);
+const RowDesc *find_row_shifted(uint64_t n2);
+// complex samples per 128-byte cache line
+constexpr uint64_t kLineSamples = 16;
 int split_variant_counts(uint64_t n, int *ncol, int *nrow);
 unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev,
                   int grid_mult);

@@ -933,6 +933,34 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     }
 }
 
+// Pass A of segments that start anywhere in a 128-byte line: column blocks
+// start at column `shift`, the first whose address is line-aligned, and the
+// last block wraps round to the columns before it (Pol::kWrap), so every
+// block reads and writes whole lines when ybuf has the input's offset
+// within a line.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    four_step_columns_shifted_kernel(const c32 *in, c32 *ybuf, const c32 *__restrict__ tw,
+                                     const c32 *__restrict__ tl, const c32 *__restrict__ th,
+                                     int sh, int n2, uint64_t batch, int shift)
+{
+    static_assert(Pol::kWrap, "shifted blocks wrap round");
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
+    const uint64_t blocks = (uint64_t)(n2 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
+        const uint64_t seg = g / blocks;
+        const int first = (int)(g - seg * blocks) * Pol::C + shift;
+        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
+                                Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
+                                in + seg * nseg, ybuf + seg * nseg, first, n2);
+    }
+}
+
 // Pass A over overlapping, windowed frames (short-time transform): frame s
 // starts at in + s * hop and its sample n is multiplied by window[n] (window
 // may be null) as the column loads read it; otherwise as
@@ -1078,6 +1106,29 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         row_tile<Sh, Pol, D>(lds, tw, Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(),
                              threadIdx.x, ybuf + seg * nseg,
                              out + seg * nseg, first, n1);
+    }
+}
+
+// Pass B with row blocks starting at row `shift` (the first whose transposed
+// store is line-aligned in out) and the last one wrapping round (Pol::kWrap).
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    four_step_rows_shifted_kernel(const c32 *ybuf, c32 *out, const c32 *__restrict__ tw,
+                                  int n1, uint64_t batch, int shift)
+{
+    static_assert(Pol::kWrap, "shifted blocks wrap round");
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n1;
+    const uint64_t blocks = (uint64_t)(n1 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
+        const uint64_t seg = g / blocks;
+        const int first = (int)(g - seg * blocks) * Pol::C + shift;
+        row_tile<Sh, Pol, D>(lds, tw, Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(),
+                             threadIdx.x, ybuf + seg * nseg, out + seg * nseg, first, n1);
     }
 }
 

@@ -123,6 +123,35 @@ def test_every_four_step_tile_variant(n):
                 assert np.all(e <= oracle.tolerance(n)), (c, r, d, e.max())
 
 
+@pytest.mark.parametrize("n", [1000, 4096, 1 << 15, 1 << 16, 1 << 18, 1 << 20, 1 << 22])
+def test_bases_off_a_line_boundary(n):
+    """Input and output base pointers anywhere in a 128-byte line (two-pass
+    plans then start their blocks mid-segment and wrap round), out of place
+    and in place; nothing outside the output range is written."""
+    import torch
+    b = 3 if n <= 1 << 18 else 2
+    x = noise(n, b, seed=n + 9).reshape(-1)
+    ref = oracle.fft_recursive(x.reshape(b, n), n)
+    for lead_in, lead_out in [(8, 8), (3, 5), (0, 13), (15, 0)]:
+        announce("n=%d batch=%d lead in %d out %d" % (n, b, lead_in, lead_out))
+        xd = torch.zeros(b * n + 16, dtype=torch.complex64, device="cuda")
+        xd[lead_in:lead_in + b * n] = torch.from_numpy(x).cuda()
+        yd = torch.zeros(b * n + 16, dtype=torch.complex64, device="cuda")
+        with fs.Plan(n, b) as p:
+            p.exec_ptr(xd.data_ptr() + 8 * lead_in, yd.data_ptr() + 8 * lead_out, 0)
+            torch.cuda.synchronize()
+            y = yd.cpu().numpy()
+            assert np.all(y[:lead_out] == 0) and np.all(y[lead_out + b * n:] == 0)
+            got = y[lead_out:lead_out + b * n].reshape(b, n)
+            assert np.all(oracle.rel_l2(got, ref) <= oracle.tolerance(n)), (lead_in, lead_out)
+            # in place at the input's offset
+            p.exec_ptr(xd.data_ptr() + 8 * lead_in, xd.data_ptr() + 8 * lead_in, 0)
+            torch.cuda.synchronize()
+            got2 = xd.cpu().numpy()[lead_in:lead_in + b * n].reshape(b, n)
+            assert np.array_equal(got2, y[lead_out:lead_out + b * n].reshape(b, n)) or \
+                np.all(oracle.rel_l2(got2, ref) <= oracle.tolerance(n))
+
+
 @pytest.mark.parametrize("n", [1 << 21, 3 * (1 << 20), 1 << 23, 1 << 24])
 def test_long_lengths_up_to_the_cap(n):
     """Segments up to the 2^24-sample cap (two passes where both halves
