@@ -13,6 +13,8 @@ using sp_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw
 using sp_strided_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
                                       uint64_t batch, uint64_t in_stride, uint64_t out_stride,
                                       const float *window, unsigned grid, hipStream_t s);
+using sp_rotated_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
+                                      uint64_t batch, int rot, unsigned grid, hipStream_t s);
 using sp_real_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
                                    const void *hw, uint64_t batch, unsigned grid,
                                    hipStream_t s);
@@ -84,6 +86,10 @@ SinglePassDesc shuffle4096_desc(int variant, int grid_mult, int nontemporal);
 SinglePassDesc split_desc(int config, int variant, int grid_mult);
 ColumnDesc split_column_desc(int config, int variant);
 RowDesc split_row_desc(int config, int variant);
+// The one-pass kernel of length n with rotated lanes (kernels_rotated.hip),
+// for outputs off a 128-byte line; null launcher if the length has none.
+// `variant` receives the table variant whose kernel it mirrors.
+sp_rotated_launch_fn rotated_launcher(uint64_t n, int *variant, const void **kernels);
 // single-pass instances with one LDS pad element every 32 (kernels_pad.hip)
 SinglePassDesc pad32_desc(int config, int variant, int grid_mult);
 // four-step tiles with radix-32 stages (kernels_radix32.hip)

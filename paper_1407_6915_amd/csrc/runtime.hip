@@ -670,6 +670,21 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
     case Plan::SINGLE: {
         const SinglePassDesc *d = p->sp;
         const uint64_t groups = (batch + d->segs_per_wg - 1) / d->segs_per_wg;
+        // an output base inside a 128-byte line: the kernel with rotated
+        // lanes puts each wave's stores back on line boundaries
+        const uint64_t out_m = ((uintptr_t)out / sizeof(c32)) % kLineSamples;
+        if (out_m) {
+            int rv = -1;
+            const void *rk[2] = {nullptr, nullptr};
+            const sp_rotated_launch_fn rl = rotated_launcher(n, &rv, rk);
+            if (rl && rv == d->variant) {
+                const unsigned grid = grid_for(rk[dir > 0], d->threads * d->segs_per_wg, groups,
+                                               p->device, p->grid_mult);
+                rl(dir, in, out, p->tw, batch, (int)((kLineSamples - out_m) % kLineSamples),
+                   grid, s);
+                break;
+            }
+        }
         const unsigned grid = grid_for(d->kernel[dir > 0], d->threads * d->segs_per_wg,
                                        groups, p->device, p->grid_mult);
         d->launch(dir, in, out, p->tw, batch, grid, s);

@@ -547,6 +547,37 @@ __global__ void __launch_bounds__(Pol::kThreads)
     }
 }
 
+// single_pass_plain_kernel with the thread -> butterfly assignment rotated
+// by `rot` (thread t of a segment takes the butterflies of t' = (t + rot)
+// mod T in every stage; any bijection is a valid Stockham schedule, since
+// the LDS exchange is addressed by element).  With rot = -(out offset
+// within a 128-byte line) the last stage's stores of each wave start on a
+// line boundary again when the output base pointer does not.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+    single_pass_rotated_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                               uint64_t batch, int rot)
+{
+    static_assert(!Pol::kPartial, "every thread of the workgroup owns butterflies");
+    static_assert((Sh::T & (Sh::T - 1)) == 0, "rotation by mask");
+    __shared__ c32 lds[Pol::kLdsElems];
+    const int slot = Pol::template col<0>((int)threadIdx.x);
+    const int t = (int)(((unsigned)Pol::template thr<0>((int)threadIdx.x) + (unsigned)rot) &
+                        (unsigned)(Sh::T - 1));
+    const int tid = slot * Sh::T + t;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const uint64_t seg = g * Pol::S + slot;
+        typename Pol::Ctx ctx{out + seg * Sh::M, seg < batch};
+        const c32 *x = in + seg * Sh::M;
+        c32 v[Sh::kMaxE];
+        using S0 = Stage<Sh, 0, 1>;
+        if (ctx.valid)
+            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+        tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
+    }
+}
+
 // single_pass_plain_kernel with the next segment's stage-0 loads issued
 // before the current segment's stages (software pipelining in registers):
 // for lengths whose LDS footprint leaves few workgroups per CU, the loads of
