@@ -152,6 +152,26 @@ def test_bases_off_a_line_boundary(n):
                 np.all(oracle.rel_l2(got2, ref) <= oracle.tolerance(n))
 
 
+def test_shifted_tiles_walk_several_tiles(monkeypatch):
+    """The line-aligned (shifted, wrapping) four-step tiles and the rotated
+    one-pass kernel on a persistent grid of one resident wave, so every
+    workgroup takes several tiles or segments in turn."""
+    import torch
+    monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
+    for n, b in [(1 << 16, 300), (4096, 4101)]:
+        x = noise(n, b, seed=n + 21).reshape(-1)
+        ref = oracle.fft_recursive(x.reshape(b, n), n)
+        announce("n=%d batch=%d lead in 5 out 3, grid_mult=1" % (n, b))
+        xd = torch.zeros(b * n + 16, dtype=torch.complex64, device="cuda")
+        xd[5:5 + b * n] = torch.from_numpy(x).cuda()
+        yd = torch.zeros(b * n + 16, dtype=torch.complex64, device="cuda")
+        with fs.Plan(n, b) as p:
+            p.exec_ptr(xd.data_ptr() + 40, yd.data_ptr() + 24, 0)
+        torch.cuda.synchronize()
+        got = yd.cpu().numpy()[3:3 + b * n].reshape(b, n)
+        assert np.all(oracle.rel_l2(got, ref) <= oracle.tolerance(n))
+
+
 @pytest.mark.parametrize("n", [1 << 21, 3 * (1 << 20), 1 << 23, 1 << 24])
 def test_long_lengths_up_to_the_cap(n):
     """Segments up to the 2^24-sample cap (two passes where both halves
