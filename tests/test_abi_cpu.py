@@ -76,6 +76,21 @@ def test_variants_compiled_for_workload_lengths():
         assert fs.variant_count(n) >= 2, n
 
 
+def test_two_pass_splits_are_balanced_and_tiled():
+    """Every two-pass length gets the most balanced split whose column and
+    row lengths have compiled tiles (radix-32 tiles included)."""
+    for k in range(15, 23):
+        n = 1 << k
+        info = fs.split_info(n)
+        assert info is not None, n
+        n1, n2, nc, nr = info
+        assert n1 * n2 == n and abs(n1.bit_length() - n2.bit_length()) <= 1, (n, n1, n2)
+        assert n1 <= n2 and nc >= 1 and nr >= 1
+    assert fs.split_info(1 << 20)[:2] == (1024, 1024)
+    assert fs.split_info(1 << 16)[:2] == (256, 256)
+    assert fs.split_info(1 << 17)[:2] == (256, 512)
+
+
 def test_split_info_and_forced_variants_are_checked():
     assert fs.split_info(4096) is None            # single pass
     assert fs.split_info(3 ** 9) is None          # radix-stage fallback
