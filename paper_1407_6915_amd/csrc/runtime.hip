@@ -380,7 +380,23 @@ unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev
 // workgroup walks tiles with a grid-stride loop, so twiddles loaded once
 // stay in registers); FFTSEG_GRID_MULT=0 gives one workgroup per tile.
 constexpr int kDefaultGridMult = 8;
-constexpr int kTwoPassGridMult = 32;  // measured best for the four-step passes
+constexpr int kTwoPassGridMult = 32;  // four-step passes without a measured choice
+
+// Four-step passes: the measured best grid by column-tile length (interleaved
+// A/B runs at 8 GiB; 128 is one workgroup per tile of a 4 GiB sub-batch at
+// 256 and 512 points)
+int two_pass_grid_mult(uint64_t n1)
+{
+    switch (n1) {
+    case 256:
+    case 512:
+        return 128;
+    case 1024:
+        return 64;
+    default:
+        return kTwoPassGridMult;
+    }
+}
 
 int env_grid_mult()
 {
@@ -438,8 +454,6 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
                                             : hip_error(e, "twiddle upload");
     }
     p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / n));
-    if (!getenv("FFTSEG_GRID_MULT"))
-        p->grid_mult = tuned_grid_mult(n, -1, kTwoPassGridMult);
     int cv = 0, rv = 0;
     uint64_t n1 = forced_n1;
     if (forced_split_variants >= 0) {
@@ -454,6 +468,10 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
     if (!split && forced_n1)
         return set_error(FFT_ERR_INVALID_ARG, "length %llu has no split with %llu columns",
                          (unsigned long long)n, (unsigned long long)forced_n1);
+    if (!getenv("FFTSEG_GRID_MULT"))
+        p->grid_mult = tuned_grid_mult(n, -1,
+                                       split ? two_pass_grid_mult((uint64_t)p->col->n1)
+                                             : kTwoPassGridMult);
     if (split) {
         p->kind = Plan::FOURSTEP;
         p->n1 = (uint64_t)p->col->n1;
