@@ -476,7 +476,12 @@ __device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw
     using S0 = Stage<Sh, 0, 1>;
     if (ctx.valid)
         st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
-    tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+    // lds holds lds_c32<kLdsElems, kSplit>() complex elements
+    if constexpr (Pol::kSplit)
+        tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
+                                         ctx);
+    else
+        tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
 // Overlapping, windowed segments (short-time transform): segment s reads
