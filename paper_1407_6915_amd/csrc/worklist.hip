@@ -261,7 +261,11 @@ __global__ void __launch_bounds__(256) clear_kernel(uint32_t *ctl, uint32_t n)
 // Task sizes: a single-pass task is `group` whole tiles of S segments
 // (about 64 KiB of input); a two-pass segment's `tiles` column (row) blocks
 // are cut into tasks of `group` blocks.  Fewer, larger tasks keep the
-// cursor's atomics off the critical path.
+// cursor's atomics off the critical path, but a 65536-point segment's blocks
+// go one per task: workgroups that claim neighbouring tasks then transform
+// the blocks of one segment side by side, and its 128-byte pieces of each
+// 2 KB row or column run reach memory close together in time (8 blocks per
+// task, walked by one workgroup in turn, were 3-5 % slower on the whole).
 struct LengthInfo {
     uint32_t n;
     bool two_pass;
@@ -280,7 +284,7 @@ const LengthInfo kLengths[] = {
     {4096, false, false, K4096, K4096, P4096::S, 2, 0, 0},
     {6000, false, false, K6000, K6000, P6000::S, 2, 0, 0},
     {16384, false, true, K16384W, K16384W, 1, 1, 0, 0},
-    {65536, true, false, K65536A, K65536B, 256 / PCol256::C, 8, 256, 256},
+    {65536, true, false, K65536A, K65536B, 256 / PCol256::C, 1, 256, 256},
     {1u << 20, true, false, K1MA, K1MB, 1024 / PCol1k::C, 16, 1024, 1024},
 };
 
