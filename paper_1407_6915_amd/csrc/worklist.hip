@@ -6,7 +6,7 @@
 // each filling one 256-thread workgroup tile:
 //   single pass  up to S whole segments of one length (S = 16 for 256, ...)
 //   two pass     one column tile (pass A) or row tile (pass B) of a
-//                four-step segment (65536 = 256 x 256, 2^20 = 1024 x 1024)
+//                65536-point segment (256 x 256)
 // Workgroups claim tasks (a few at a time) through an atomic cursor in list
 // order.  The kernel runs twice: first over every pass-A task and every
 // single-pass task (longest first), then over every pass-B task.  The
@@ -18,6 +18,13 @@
 // LDS exchanges) does not fit the 256-thread workgroup, so they run in a
 // launch of their own between the two, one segment per workgroup tile,
 // instead of as two passes of 128 x 128.
+// 2^20-point segments leave the work-list kernel altogether: a 1024-point
+// column tile that fits its workgroup (256 threads, 35 KB of LDS) holds only
+// 4 columns, 32-byte pieces of each line, and ran at a quarter of the plain
+// four-step kernels' rate.  Each run of consecutive 2^20-point entries whose
+// inputs and outputs advance by one segment goes through a four-step plan of
+// that length instead (its 16-column radix-32 tiles, 512 threads, and its
+// line-shifted forms for runs that start inside a line).
 #include "fftseg.h"
 #include "runtime.hpp"
 #include "tile.hpp"
@@ -40,8 +47,7 @@ enum Kind : uint32_t {
     K16384W,
     K65536A,
     K65536B,
-    K1MA,
-    K1MB,
+    K1M,  // 2^20: through the four-step plan, no tasks
     KCOUNT
 };
 
@@ -91,16 +97,12 @@ using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false, 1, false, false, fa
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
 using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
 using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
-using Sh1k = Shape<1024, 64, Radices<16, 16, 4>>;
-using PCol1k = ColumnPolicy<Sh1k, 4, 4, true, 0, false, 1, false, false, true>;
-using PRow1k = RowPolicy<Sh1k, 4, 4, true, 0, false, 1, false, false, true>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLdsElems =
     cmax(cmax(cmax(P256::kLdsElems, P1000::kLdsElems), cmax(P1024::kLdsElems, P1536::kLdsElems)),
          cmax(cmax(P4096::kLdsElems, lds_c32<P6000::kLdsElems, P6000::kSplit>()),
-              cmax(cmax(PCol256::kLdsElems, PRow256::kLdsElems),
-                   cmax(PCol1k::kLdsElems, PRow1k::kLdsElems))));
+              cmax(PCol256::kLdsElems, PRow256::kLdsElems)));
 
 static_assert(4 * (kLdsElems * sizeof(c32) + sizeof(uint32_t)) <= 160 * 1024,
               "four workgroups must fit the 160 KB of LDS of a CU");
@@ -108,8 +110,7 @@ static_assert(P256::kThreads <= kThreads && P1000::kThreads <= kThreads &&
                   P1024::kThreads <= kThreads && P1536::kThreads <= kThreads &&
                   P4096::kThreads <= kThreads && P6000::kThreads <= kThreads,
               "single-pass routines must fit the workgroup");
-static_assert(PCol256::kThreads == kThreads && PRow256::kThreads == kThreads &&
-                  PCol1k::kThreads == kThreads && PRow1k::kThreads == kThreads,
+static_assert(PCol256::kThreads == kThreads && PRow256::kThreads == kThreads,
               "two-pass routines use the whole workgroup");
 
 // tasks claimed per atomic on the cursor
@@ -210,14 +211,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
             case K65536A:
                 run_columns<Sh256c, PCol256, D>(lds, tb, t, items, in, ybuf, tid, 256);
                 break;
-            case K1MA:
-                run_columns<Sh1k, PCol1k, D>(lds, tb, t, items, in, ybuf, tid, 1024);
-                break;
             case K65536B:
                 run_rows<Sh256c, PRow256, D>(lds, tb, t, items, ybuf, out, tid, 256);
-                break;
-            case K1MB:
-                run_rows<Sh1k, PRow1k, D>(lds, tb, t, items, ybuf, out, tid, 1024);
                 break;
             default: break;
             }
@@ -274,6 +269,7 @@ struct LengthInfo {
     int per_tile; // single pass: segments per tile (S); two pass: blocks per pass
     int group;    // tiles (blocks) per task
     int n1, n2;
+    bool planned; // runs through a four-step plan, not the work-list kernel
 };
 
 const LengthInfo kLengths[] = {
@@ -285,7 +281,7 @@ const LengthInfo kLengths[] = {
     {6000, false, false, K6000, K6000, P6000::S, 2, 0, 0},
     {16384, false, true, K16384W, K16384W, 1, 1, 0, 0},
     {65536, true, false, K65536A, K65536B, 256 / PCol256::C, 1, 256, 256},
-    {1u << 20, true, false, K1MA, K1MB, 1024 / PCol1k::C, 16, 1024, 1024},
+    {1u << 20, true, false, K1M, K1M, 0, 0, 1024, 1024, true},
 };
 
 const LengthInfo *length_info(uint32_t n)
@@ -314,6 +310,14 @@ struct WorkList {
     unsigned wide_grid = 1;
     const c32 *wide_tw = nullptr;        // its twiddle table (one of table_mem)
     uint64_t counts[wl::KCOUNT] = {};
+    // planned lengths: runs of consecutive entries, and the plan they go
+    // through (built for at least the longest run)
+    struct PlanRun {
+        uint64_t in_off, out_off, count;
+    };
+    std::vector<PlanRun> plan_runs;
+    uint64_t plan_len = 0, plan_max_run = 0;
+    Plan *plan = nullptr;
     uint64_t samples = 0;
     size_t y_bytes = 0;
     unsigned grid = 1;
@@ -363,6 +367,10 @@ struct WorkList {
         for (void *p : table_mem)
             if (p)
                 (void)hipFree(p);
+        if (plan) {
+            plan_free(plan);
+            delete plan;
+        }
     }
 };
 
@@ -396,6 +404,8 @@ int wl_tables(WorkList *w)
     };
     int st;
     for (const LengthInfo &L : kLengths) {
+        if (L.planned)
+            continue;  // the plan has its own tables
         if (!L.two_pass) {
             if ((st = up(roots(L.n), &tables[L.a].tw)) != FFT_OK)
                 return st;
@@ -536,12 +546,33 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     hitems.reserve(n);
     std::vector<Task> a_tasks, s_tasks, b_tasks;
     std::vector<Item> wide_items;
+    std::vector<WorkList::PlanRun> plan_runs;
+    uint64_t plan_len = 0, plan_max_run = 0;
     uint64_t y_samples = 0;
     uint32_t two_pass = 0;
     uint64_t counts[KCOUNT] = {};
     for (int li = (int)NL - 1; li >= 0; --li) {
         const LengthInfo &L = kLengths[li];
         const auto &b = bucket[li];
+        if (L.planned) {
+            // bucket entries are in list order: consecutive entries whose
+            // input and output both advance by one segment form a run
+            for (uint32_t idx : b) {
+                const uint64_t ia = items[idx].in_off, oa = items[idx].out_off;
+                if (!plan_runs.empty() &&
+                    plan_runs.back().in_off + plan_runs.back().count * L.n == ia &&
+                    plan_runs.back().out_off + plan_runs.back().count * L.n == oa)
+                    ++plan_runs.back().count;
+                else
+                    plan_runs.push_back({ia, oa, 1});
+                plan_max_run = std::max(plan_max_run, plan_runs.back().count);
+            }
+            if (!b.empty())
+                plan_len = L.n;
+            counts[L.a] += b.size();
+            two_pass += (uint32_t)b.size();
+            continue;
+        }
         if (L.wide) {
             for (uint32_t idx : b)
                 wide_items.push_back({items[idx].in_off, items[idx].out_off, 0});
@@ -603,6 +634,17 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     w->n_two_pass = two_pass;
     w->wide_first = wide_first;
     w->n_wide = (uint32_t)wide_items.size();
+    // a captured graph holds the planned runs' offsets and counts as launch
+    // arguments (the tasks it reads from device memory)
+    const auto same_run = [](const WorkList::PlanRun &x, const WorkList::PlanRun &y) {
+        return x.in_off == y.in_off && x.out_off == y.out_off && x.count == y.count;
+    };
+    if (plan_runs.size() != w->plan_runs.size() ||
+        !std::equal(plan_runs.begin(), plan_runs.end(), w->plan_runs.begin(), same_run))
+        w->drop_graph();
+    w->plan_runs.swap(plan_runs);
+    w->plan_len = plan_len;
+    w->plan_max_run = plan_max_run;
     w->y_bytes = y_samples * sizeof(c32);
     std::memcpy(w->counts, counts, sizeof(counts));
     return FFT_OK;
@@ -654,6 +696,28 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
                 FFT_OK)
             return st;
     }
+    if (w->plan_len && (!w->plan || w->plan->n != w->plan_len ||
+                        w->plan->batch < w->plan_max_run)) {
+        // a plan for at least the longest run (at least twice the old one,
+        // so that growing runs rebuild it rarely); its scratch may be in use
+        const uint64_t batch =
+            std::max<uint64_t>(w->plan_max_run,
+                               w->plan && w->plan->n == w->plan_len ? 2 * w->plan->batch : 1);
+        (void)hipDeviceSynchronize();
+        w->drop_graph();
+        if (w->plan) {
+            plan_free(w->plan);
+            delete w->plan;
+            w->plan = nullptr;
+        }
+        Plan *p = new Plan();
+        if ((st = plan_build(p, w->plan_len, batch, w->dir, -1)) != FFT_OK) {
+            plan_free(p);
+            delete p;
+            return st;
+        }
+        w->plan = p;
+    }
     const size_t tb = tasks.size() * sizeof(Task), ib = hitems.size() * sizeof(Item);
     hipError_t e;
     if (!w->stage_done && (e = hipEventCreateWithFlags(&w->stage_done, hipEventDisableTiming)) !=
@@ -702,6 +766,14 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
 int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
 {
     using namespace wl;
+    // planned runs first: they touch only their own ranges and the plan's
+    // scratch, so their order against the work-list launches is free
+    for (const WorkList::PlanRun &r : w->plan_runs) {
+        const int st = plan_enqueue(w->plan, (const c32 *)in + r.in_off,
+                                    (c32 *)out + r.out_off, r.count, s);
+        if (st != FFT_OK)
+            return st;
+    }
     if (w->n_tasks == 0 && w->n_wide == 0)
         return set_ok();
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, w->d_ctl, 2u);
@@ -744,7 +816,7 @@ int wl_check_io(WorkList *w, const void *in, void *out)
         return set_error(FFT_ERR_INVALID_ARG, "in_base/out_base must not be NULL");
     if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
         return set_error(FFT_ERR_ALIGNMENT, "bases must be 8-byte aligned");
-    if (w->n_tasks == 0 && w->n_wide == 0)
+    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
         return FFT_OK;
     if (in == out && !w->in_place_ok)
         return set_error(FFT_ERR_OVERLAP,
@@ -845,7 +917,7 @@ extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, 
     int st = wl_check_io(w, in_base, out_base);
     if (st != FFT_OK)
         return st;
-    if (w->n_tasks == 0 && w->n_wide == 0)
+    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
         return set_ok();
     hipError_t e;
     if (!w->graph_exec || w->graph_in != in_base || w->graph_out != out_base) {
@@ -910,6 +982,7 @@ extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
                      ",\"two_pass_segments\":" + std::to_string(w->n_two_pass) +
                      ",\"wide_segments\":" + std::to_string(w->n_wide) +
                      ",\"wide_grid\":" + std::to_string(w->wide_grid) +
+                     ",\"plan_runs\":" + std::to_string(w->plan_runs.size()) +
                      ",\"samples\":" + std::to_string(w->samples) +
                      ",\"scratch_bytes\":" + std::to_string(w->y_bytes) +
                      ",\"in_place_ok\":" + (w->in_place_ok ? "true" : "false") +

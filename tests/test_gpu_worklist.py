@@ -143,6 +143,50 @@ def test_two_pass_segments_at_any_line_offset(lead):
         check_all(x, yd.cpu().numpy(), in_off, out_off, lengths, direction)
 
 
+def test_long_segments_go_through_the_plan_in_runs():
+    """2^20-point entries run through a four-step plan, one call per run of
+    consecutive entries whose inputs and outputs advance by one segment:
+    runs of 3, 2 and 1 (the second starting inside a cache line), mixed with
+    work-list lengths, in place and out of place; then graph replays across
+    a reset whose longer run makes the plan grow (the old graph, which holds
+    the old runs, must not be replayed)."""
+    import torch
+    m = 1 << 20
+    lengths = np.array([m, m, m, 4096, m, m, 65536, m], np.int64)
+    in_off = np.array([0, m, 2 * m, 3 * m, 3 * m + 4099, 4 * m + 4099, 5 * m + 4099,
+                       5 * m + 4099 + 65536], np.int64)
+    total = int(in_off[-1] + m)
+    announce("work list 2^20 runs, %d samples" % total)
+    x = siggen.Signal(seed=16, seg_len=1, sigma=1.0).samples(0, total)
+    with fs.WorkList(to_entries(in_off, in_off, lengths)) as wl:
+        assert wl.describe()["plan_runs"] == 3
+        xd = torch.from_numpy(x).cuda()
+        wl.exec(xd, xd)                                     # in place
+        wl.status()
+        check_all(x, xd.cpu().numpy(), in_off, in_off, lengths)
+        # out of place, outputs in reverse slot order: no entry stays in a run
+        out_off, out_total = packed(lengths[::-1], gap=3)
+        out_off = out_off[::-1].copy()
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros(out_total, dtype=torch.complex64, device="cuda")
+        wl.reset(to_entries(in_off, out_off, lengths))
+        assert wl.describe()["plan_runs"] == 6
+        wl.exec(xd, yd, graph=True)
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        check_all(x, yd.cpu().numpy(), in_off, out_off, lengths, sample=[0, 4, 5, 6])
+        # a run of 5 (longer than any before): the plan grows, the graph is
+        # captured again
+        lengths2 = np.array([m] * 5 + [1024], np.int64)
+        off2 = np.concatenate([np.arange(5) * m, [5 * m]]).astype(np.int64)
+        wl.reset(to_entries(off2, off2, lengths2))
+        assert wl.describe()["plan_runs"] == 1
+        yd.zero_()
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        check_all(x, yd.cpu().numpy(), off2, off2, lengths2, sample=[0, 4, 5])
+
+
 def test_in_place_and_overlap_rules():
     import torch
     lengths = np.array([4096, 65536, 256, 16384, 1000, 6000, 1536, 1024] * 3, np.int64)
