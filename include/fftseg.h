@@ -248,15 +248,20 @@ typedef struct {
 typedef struct fftseg_worklist *fft_worklist_t;
 
 /* 1 if segment_len has a work-list routine (256, 1000, 1024, 1536, 4096,
- * 6000 and 16384 in one pass; 65536 and 2^20 in two passes), else 0. */
+ * 6000 and 16384 in one pass; 65536 in two passes; 2^20 through a
+ * four-step plan the work list keeps), else 0. */
 int fft_worklist_supported(uint32_t segment_len);
 
 /* Compile n entries into workgroup tasks: segments are grouped by length,
  * packed S per tile for short lengths, split into column/row tiles for the
  * two-pass lengths; 16384-point segments become "wide" tiles of their own
- * launch (one 512-thread workgroup per segment).  The task list,
- * per-length twiddle tables and the two-pass scratch (one Y buffer per
- * two-pass segment) are uploaded once.  Output ranges must not overlap
+ * launch (one 512-thread workgroup per segment).  2^20-point entries get no
+ * tasks: each run of consecutive ones whose input and output offsets both
+ * advance by 2^20 goes through a four-step plan of that length, which the
+ * work list builds (or rebuilds, after a device-wide synchronisation) for
+ * the longest run seen.  The task list, per-length twiddle tables and the
+ * two-pass scratch (one Y buffer per 65536-point segment) are uploaded
+ * once.  Output ranges must not overlap
  * (FFT_ERR_OVERLAP); an unsupported length gives FFT_ERR_UNSUPPORTED_LENGTH.
  * n may be 0 (an empty list to fill later with fft_worklist_reset).  All
  * entry checks run before any device work.  NULL on error. */
@@ -270,7 +275,8 @@ fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direct
  * list is re-filled with whatever segments are ready. */
 int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, void *stream);
 
-/* Run every entry: a cursor-clearing kernel, then the persistent kernel
+/* Run every entry: the planned 2^20-point runs (their plan's two passes
+ * per run, in sub-batches), a cursor-clearing kernel, then the persistent kernel
  * twice (workgroups claim tasks through an atomic cursor): first over the
  * first-pass tiles of the two-pass segments and the one-pass tiles, then
  * over the second-pass tiles, which the launch boundary orders after their
@@ -283,7 +289,8 @@ int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, voi
 int fft_exec_worklist(fft_worklist_t wl, const void *in_base, void *out_base, void *stream);
 
 /* Same work, launched as a hipGraph captured on first use (and re-captured
- * when in_base/out_base change). */
+ * when in_base/out_base change, or a reset changes the planned runs or the
+ * grids). */
 int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_base,
                             void *stream);
 
@@ -293,8 +300,8 @@ int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_ba
  * FFT_ERR_TIMEOUT is not returned here.) */
 int fft_worklist_status(fft_worklist_t wl, void *stream);
 
-/* JSON summary (items, tasks, wide segments, per-length counts, scratch
- * bytes, grids). */
+/* JSON summary (items, tasks, wide segments, planned runs, per-length
+ * counts, scratch bytes, grids). */
 int fft_worklist_describe(fft_worklist_t wl, char *buf, size_t len);
 
 /* Synchronise the device, then free the work list.  NULL is a no-op. */
