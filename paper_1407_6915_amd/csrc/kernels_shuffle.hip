@@ -81,8 +81,6 @@ __device__ __forceinline__ int pad(int i) { return i + (i >> kPad); }
 
 // The twiddles of stages 1 and 2 stay in registers across the segments of
 // the persistent loop (about 140 VGPRs: 2 waves per SIMD).
-// The twiddles of stages 1 and 2 stay in registers across the segments of
-// the persistent loop.
 // LoadNT / StoreNT: non-temporal global loads / stores.  The 32-byte runs of
 // stage 0 are better read through the cache, whose lines the other waves of
 // the workgroup then hit.
