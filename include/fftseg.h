@@ -272,7 +272,11 @@ fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direct
  * synchronisation, only when too small).  The new task list is uploaded
  * from pinned staging on `stream`, so it is ordered after earlier launches
  * and before later ones on that stream.  For continuous batching: one work
- * list is re-filled with whatever segments are ready. */
+ * list is re-filled with whatever segments are ready.  Entries that fail the
+ * checks leave the previous ones in force; a reset that fails after them
+ * (device memory for the grown arrays or the 2^20-point plan) leaves the
+ * work list unable to run (FFT_ERR_INVALID_ARG from the exec calls) until a
+ * reset succeeds. */
 int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, void *stream);
 
 /* Run every entry: the planned 2^20-point runs (their plan's two passes

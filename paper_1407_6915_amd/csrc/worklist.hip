@@ -320,6 +320,9 @@ struct WorkList {
     std::vector<PlanRun> plan_runs;
     uint64_t plan_len = 0, plan_max_run = 0;
     Plan *plan = nullptr;
+    // false while the entries compiled last lack their device arrays or
+    // plan (a reset that failed after replacing them): nothing may run
+    bool ready = false;
     uint64_t samples = 0;
     size_t y_bytes = 0;
     unsigned grid = 1;
@@ -682,7 +685,8 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
     std::vector<Item> hitems;
     int st = wl_compile(w, items, n, tasks, hitems);
     if (st != FFT_OK)
-        return st;
+        return st;  // entries rejected: the previous ones still stand
+    w->ready = false;
     const size_t need_ctl = 2;  // one task cursor per launch
     const size_t need_y = w->y_bytes / sizeof(c32);
     if (tasks.size() > w->cap_tasks || hitems.size() > w->cap_items || need_ctl > w->cap_ctl ||
@@ -762,6 +766,7 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
         w->drop_graph();  // the captured launches have the old grids
     w->grid = g;
     w->wide_grid = gw;
+    w->ready = true;
     return set_ok();
 }
 
@@ -818,6 +823,9 @@ int wl_check_io(WorkList *w, const void *in, void *out)
         return set_error(FFT_ERR_INVALID_ARG, "in_base/out_base must not be NULL");
     if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))
         return set_error(FFT_ERR_ALIGNMENT, "bases must be 8-byte aligned");
+    if (!w->ready)
+        return set_error(FFT_ERR_INVALID_ARG,
+                         "the last reset failed after taking its entries: reset again");
     if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
         return FFT_OK;
     if (in == out && !w->in_place_ok)

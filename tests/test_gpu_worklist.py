@@ -187,6 +187,35 @@ def test_long_segments_go_through_the_plan_in_runs():
         check_all(x, yd.cpu().numpy(), off2, off2, lengths2, sample=[0, 4, 5])
 
 
+def test_failed_reset_refuses_to_run_until_the_next_reset():
+    """A reset whose entries pass the checks but whose two-pass scratch
+    cannot be allocated (600000 segments of 65536 points need 315 GB)
+    returns FFT_ERR_OUT_OF_MEMORY; the work list then refuses to run,
+    without a launch, until a reset succeeds."""
+    import torch
+    n = 1024
+    announce("work list failed reset")
+    x = siggen.Signal(seed=17, seg_len=n, sigma=1.0).samples(0, 4 * n)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(4 * n, dtype=torch.complex64, device="cuda")
+    offs = np.arange(4, dtype=np.int64) * n
+    small = to_entries(offs, offs, np.full(4, n, np.int64))
+    big_n = 600000
+    big_off = np.arange(big_n, dtype=np.int64) * 65536
+    big = to_entries(big_off, big_off, np.full(big_n, 65536, np.int64))
+    with fs.WorkList(small) as wl:
+        with pytest.raises(fs.FFTError) as e:
+            wl.reset(big)
+        assert e.value.name == "FFT_ERR_OUT_OF_MEMORY"
+        with pytest.raises(fs.FFTError) as e:
+            wl.exec(xd, yd)
+        assert e.value.name == "FFT_ERR_INVALID_ARG"
+        wl.reset(small)
+        wl.exec(xd, yd)
+        wl.status()
+    check_all(x, yd.cpu().numpy(), offs, offs, np.full(4, n, np.int64))
+
+
 def test_in_place_and_overlap_rules():
     import torch
     lengths = np.array([4096, 65536, 256, 16384, 1000, 6000, 1536, 1024] * 3, np.int64)
