@@ -170,14 +170,15 @@ class GpuExecutor:
     def reserve(self, max_launch_samples: int) -> None:
         """Grow the work list's device arrays to what a launch of up to
         max_launch_samples can need (task and item lists of the shortest
-        length, two-pass scratch of the longest), so that no later reset
-        has to synchronise the device and reallocate while jobs are in
-        flight.  Only the capacities are kept."""
+        length, the two-pass scratch of 65536-point segments, the four-step
+        plan of the 2^20-point ones), so that no later reset has to
+        synchronise the device and reallocate while jobs are in flight.
+        Only the capacities are kept."""
         import numpy as np
         from . import worklist_supported
         lens = [n for n in (256, 1000, 1024, 1536, 4096, 6000, 16384, 65536, 1 << 20)
                 if worklist_supported(n)]
-        for n in (min(lens), max(lens)):
+        for n in sorted({min(lens), 65536, max(lens)} & set(lens)):
             cnt = max(1, max_launch_samples // n)
             ent = np.zeros(cnt, dtype=[("in_off", "<u8"), ("out_off", "<u8"),
                                        ("segment_len", "<u4"), ("job", "<u4")])
