@@ -279,8 +279,26 @@ fft_worklist_t fft_worklist_create(const fft_work_t *items, size_t n, int direct
  * reset succeeds. */
 int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, void *stream);
 
-/* Run every entry: the planned 2^20-point runs (their plan's two passes
- * per run, in sub-batches), a cursor-clearing kernel, then the persistent kernel
+/* One call per uneven batch: transform the n entries of `items` (direction
+ * FFT_FORWARD or FFT_INVERSE) from in_base to out_base on `stream`, as
+ * fft_worklist_create + fft_worklist_exec would, with the same entry and
+ * buffer rules and errors.  The work list behind the call is kept by the
+ * library, one per (device, direction, stream), and re-filled on each call
+ * (fft_worklist_reset): calls on one stream are ordered by it and may
+ * share that work list's device arrays and scratch; calls on different
+ * streams use different ones.  `items` is read before the call returns.
+ * The kept work lists hold their device memory until
+ * fft_worklist_cache_clear. */
+int fft_exec_worklist(const fft_work_t *items, size_t n, int direction,
+                      const void *in_base, void *out_base, void *stream);
+
+/* Synchronise the device and free the work lists kept by
+ * fft_exec_worklist (a later call builds them again). */
+int fft_worklist_cache_clear(void);
+
+/* Run every entry of a work list made by fft_worklist_create: the planned
+ * 2^20-point runs (their plan's two passes per run, in sub-batches), a
+ * cursor-clearing kernel, then the persistent kernel
  * twice (workgroups claim tasks through an atomic cursor): first over the
  * first-pass tiles of the two-pass segments and the one-pass tiles, then
  * over the second-pass tiles, which the launch boundary orders after their
@@ -290,12 +308,14 @@ int fft_worklist_reset(fft_worklist_t wl, const fft_work_t *items, size_t n, voi
  * buffer's allocation (FFT_ERR_BOUNDS).  in_base == out_base is allowed
  * when each entry's output range either equals its input range or overlaps
  * no input range (FFT_ERR_OVERLAP otherwise).  Asynchronous on stream. */
-int fft_exec_worklist(fft_worklist_t wl, const void *in_base, void *out_base, void *stream);
+int fft_worklist_exec(fft_worklist_t wl, const void *in_base, void *out_base, void *stream);
 
-/* Same work, launched as a hipGraph captured on first use (and re-captured
- * when in_base/out_base change, or a reset changes the planned runs or the
- * grids). */
-int fft_exec_worklist_graph(fft_worklist_t wl, const void *in_base, void *out_base,
+/* Same work, launched as a hipGraph captured on first use.  The captured
+ * launches hold the bases, task counts and splits, grids, device arrays and
+ * planned runs as fixed arguments; the graph is captured again whenever any
+ * of them differs from the capture (new bases, or a reset that changes
+ * them). */
+int fft_worklist_exec_graph(fft_worklist_t wl, const void *in_base, void *out_base,
                             void *stream);
 
 /* Synchronise `stream` and report whether the last run on it completed:

@@ -127,8 +127,10 @@ def lib():
     _sig(L, "fft_worklist_supported", i32, [ctypes.c_uint32])
     _sig(L, "fft_worklist_create", vp, [ctypes.POINTER(WorkItem), sz, i32])
     _sig(L, "fft_worklist_reset", i32, [vp, ctypes.POINTER(WorkItem), sz, vp])
-    _sig(L, "fft_exec_worklist", i32, [vp, vp, vp, vp])
-    _sig(L, "fft_exec_worklist_graph", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_worklist_exec", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_worklist_exec_graph", i32, [vp, vp, vp, vp])
+    _sig(L, "fft_exec_worklist", i32, [ctypes.POINTER(WorkItem), sz, i32, vp, vp, vp])
+    _sig(L, "fft_worklist_cache_clear", i32, [])
     _sig(L, "fft_worklist_status", i32, [vp, vp])
     _sig(L, "fft_worklist_describe", i32, [vp, ctypes.c_char_p, sz])
     _sig(L, "fft_worklist_destroy", i32, [vp])
@@ -481,7 +483,7 @@ class WorkList:
         self.n_items = n
 
     def exec_ptr(self, in_base: int, out_base: int, stream: int = 0, graph: bool = False):
-        f = lib().fft_exec_worklist_graph if graph else lib().fft_exec_worklist
+        f = lib().fft_worklist_exec_graph if graph else lib().fft_worklist_exec
         _check(f(self.handle, in_base, out_base, stream))
 
     def exec(self, x, out, stream=None, graph: bool = False):
@@ -518,6 +520,27 @@ class WorkList:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def exec_worklist_ptr(entries, in_base: int, out_base: int, direction: int = FORWARD,
+                      stream: int = 0) -> None:
+    """One call per uneven batch (fft_exec_worklist): ``entries`` as for
+    WorkList, raw device base pointers."""
+    items, n = WorkList._items(entries)
+    _check(lib().fft_exec_worklist(items, n, direction, in_base, out_base, stream))
+
+
+def exec_worklist(entries, x, out, direction: int = FORWARD, stream=None):
+    """fft_exec_worklist on torch complex64 GPU tensors holding every
+    entry's range; returns ``out``."""
+    exec_worklist_ptr(entries, _tensor_ptr(x, 0, "x"), _tensor_ptr(out, 0, "out"), direction,
+                      _stream_handle(stream))
+    return out
+
+
+def worklist_cache_clear() -> None:
+    """Free the work lists kept by fft_exec_worklist."""
+    _check(lib().fft_worklist_cache_clear())
 
 
 def worklist_supported(n: int) -> bool:

@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -339,11 +340,53 @@ struct WorkList {
     void *h_stage = nullptr;
     size_t cap_stage = 0;
     hipEvent_t stage_done = nullptr;
-    // graph replay
+    // graph replay: the captured launches hold every value of LaunchKey
+    // as a fixed argument, so the graph is replayed only while the current
+    // entries give the same key
+    struct LaunchKey {
+        const void *in = nullptr;
+        void *out = nullptr;
+        uint32_t n_tasks = 0, n_first = 0, wide_first = 0, n_wide = 0;
+        unsigned grid = 0, wide_grid = 0;
+        const void *tasks = nullptr, *items = nullptr, *ctl = nullptr, *y = nullptr;
+        const Plan *plan = nullptr;
+        std::vector<PlanRun> runs;
+        bool operator==(const LaunchKey &o) const
+        {
+            if (in != o.in || out != o.out || n_tasks != o.n_tasks || n_first != o.n_first ||
+                wide_first != o.wide_first || n_wide != o.n_wide || grid != o.grid ||
+                wide_grid != o.wide_grid || tasks != o.tasks || items != o.items ||
+                ctl != o.ctl || y != o.y || plan != o.plan || runs.size() != o.runs.size())
+                return false;
+            for (size_t i = 0; i < runs.size(); ++i)
+                if (runs[i].in_off != o.runs[i].in_off || runs[i].out_off != o.runs[i].out_off ||
+                    runs[i].count != o.runs[i].count)
+                    return false;
+            return true;
+        }
+    };
+    LaunchKey key(const void *in, void *out) const
+    {
+        LaunchKey k;
+        k.in = in;
+        k.out = out;
+        k.n_tasks = n_tasks;
+        k.n_first = n_first;
+        k.wide_first = wide_first;
+        k.n_wide = n_wide;
+        k.grid = grid;
+        k.wide_grid = wide_grid;
+        k.tasks = d_tasks;
+        k.items = d_items;
+        k.ctl = d_ctl;
+        k.y = d_y;
+        k.plan = plan;
+        k.runs = plan_runs;
+        return k;
+    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    const void *graph_in = nullptr;
-    void *graph_out = nullptr;
+    LaunchKey graph_key;
     hipStream_t capture_stream = nullptr;
 
     void drop_graph()
@@ -639,14 +682,6 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     w->n_two_pass = two_pass;
     w->wide_first = wide_first;
     w->n_wide = (uint32_t)wide_items.size();
-    // a captured graph holds the planned runs' offsets and counts as launch
-    // arguments (the tasks it reads from device memory)
-    const auto same_run = [](const WorkList::PlanRun &x, const WorkList::PlanRun &y) {
-        return x.in_off == y.in_off && x.out_off == y.out_off && x.count == y.count;
-    };
-    if (plan_runs.size() != w->plan_runs.size() ||
-        !std::equal(plan_runs.begin(), plan_runs.end(), w->plan_runs.begin(), same_run))
-        w->drop_graph();
     w->plan_runs.swap(plan_runs);
     w->plan_len = plan_len;
     w->plan_max_run = plan_max_run;
@@ -762,8 +797,6 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
                                 : (const void *)&worklist_wide_kernel<1>;
     const unsigned gw = grid_for(kw, PWide::kThreads, std::max<uint64_t>(1, w->n_wide), w->device,
                                  kWideGridMult);
-    if (g != w->grid || gw != w->wide_grid)
-        w->drop_graph();  // the captured launches have the old grids
     w->grid = g;
     w->wide_grid = gw;
     w->ready = true;
@@ -906,7 +939,7 @@ extern "C" int fft_worklist_reset(fft_worklist_t wlh, const fft_work_t *items, s
     }
 }
 
-extern "C" int fft_exec_worklist(fft_worklist_t wlh, const void *in_base, void *out_base,
+extern "C" int fft_worklist_exec(fft_worklist_t wlh, const void *in_base, void *out_base,
                                  void *stream)
 {
     WorkList *w = reinterpret_cast<WorkList *>(wlh);
@@ -918,7 +951,7 @@ extern "C" int fft_exec_worklist(fft_worklist_t wlh, const void *in_base, void *
     return wl_enqueue(w, in_base, out_base, (hipStream_t)stream);
 }
 
-extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, void *out_base,
+extern "C" int fft_worklist_exec_graph(fft_worklist_t wlh, const void *in_base, void *out_base,
                                        void *stream)
 {
     WorkList *w = reinterpret_cast<WorkList *>(wlh);
@@ -930,7 +963,8 @@ extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, 
     if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
         return set_ok();
     hipError_t e;
-    if (!w->graph_exec || w->graph_in != in_base || w->graph_out != out_base) {
+    WorkList::LaunchKey k = w->key(in_base, out_base);
+    if (!w->graph_exec || !(w->graph_key == k)) {
         w->drop_graph();
         if (!w->capture_stream &&
             (e = hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -953,8 +987,7 @@ extern "C" int fft_exec_worklist_graph(fft_worklist_t wlh, const void *in_base, 
             w->graph_exec = nullptr;
             return hip_error(e, "hipGraphInstantiate");
         }
-        w->graph_in = in_base;
-        w->graph_out = out_base;
+        w->graph_key = std::move(k);
     }
     if ((e = hipGraphLaunch(w->graph_exec, (hipStream_t)stream)) != hipSuccess)
         return hip_error(e, "hipGraphLaunch");
@@ -1022,6 +1055,73 @@ extern "C" int fft_worklist_destroy(fft_worklist_t wlh)
         (void)hipDeviceSynchronize();
         delete w;
     }
+    return set_ok();
+}
+
+// ---------------------------------------------------------------------------
+// One call per batch: the work lists behind it are kept per (device,
+// direction, stream).  Calls on one stream are ordered by the stream, so
+// they may share one work list's device arrays and scratch; calls on
+// different streams get different work lists.  Kept until
+// fft_worklist_cache_clear (never freed by a static destructor: HIP may be
+// finalised before it would run).
+namespace fftseg {
+namespace {
+struct CachedList {
+    int device;
+    int dir;
+    void *stream;
+    WorkList *w;
+};
+std::mutex g_cache_mu;
+std::vector<CachedList> g_cache;
+}  // namespace
+}  // namespace fftseg
+
+extern "C" int fft_exec_worklist(const fft_work_t *items, size_t n, int direction,
+                                 const void *in_base, void *out_base, void *stream)
+{
+    try {
+        if (!items && n)
+            return set_error(FFT_ERR_INVALID_ARG, "items is NULL");
+        if (direction != FFT_FORWARD && direction != FFT_INVERSE)
+            return set_error(FFT_ERR_INVALID_ARG, "direction must be -1 or +1");
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FFT_ERR_HIP, "no HIP device available");
+        }
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        WorkList *w = nullptr;
+        for (CachedList &c : g_cache)
+            if (c.device == dev && c.dir == direction && c.stream == stream)
+                w = c.w;
+        int st;
+        if (!w) {
+            // an empty list first: its tables and arrays, then the entries
+            fft_worklist_t h = fft_worklist_create(nullptr, 0, direction);
+            if (!h)
+                return last_status();
+            w = reinterpret_cast<WorkList *>(h);
+            g_cache.push_back({dev, direction, stream, w});
+        }
+        if ((st = wl_reset(w, items, n, (hipStream_t)stream)) != FFT_OK ||
+            (st = wl_check_io(w, in_base, out_base)) != FFT_OK)
+            return st;
+        return wl_enqueue(w, in_base, out_base, (hipStream_t)stream);
+    } catch (...) {
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+extern "C" int fft_worklist_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!g_cache.empty())
+        (void)hipDeviceSynchronize();
+    for (CachedList &c : g_cache)
+        delete c.w;
+    g_cache.clear();
     return set_ok();
 }
 

@@ -152,3 +152,15 @@ def test_worklist_output_overlap_checked_on_runs(entries, ok):
         assert e.value.name in ("FFT_ERR_HIP", "FFT_ERR_OUT_OF_MEMORY"), e.value
     else:
         assert e.value.name == "FFT_ERR_OVERLAP", e.value
+
+
+def test_one_call_worklist_checks_arguments():
+    """The one-call form refuses a bad direction or a NULL list before it
+    looks for a device."""
+    L = fs.lib()
+    assert L.fft_exec_worklist(None, 3, -1, None, None, None) == -1
+    ent = _work([(0, 0, 1024)])
+    items = ent.ctypes.data_as(ctypes.POINTER(fs.WorkItem))
+    assert L.fft_exec_worklist(items, 1, 0, None, None, None) == -1
+    assert "direction" in fs.last_error()
+    assert L.fft_worklist_cache_clear() == 0

@@ -297,3 +297,99 @@ def test_uneven_workload_full_size():
             assert e <= oracle.tolerance(n), (n, i, e)
             worst = max(worst, e / oracle.tolerance(n))
     print("  sampled 16 per length, worst error / bound %.3f" % worst, flush=True)
+
+
+def test_graph_recaptured_when_a_reset_changes_launch_arguments():
+    """The graph's launches hold the task counts and splits, the wide range
+    and the grids as fixed arguments.  Resets that keep the planned runs and
+    the grid but change those must not replay the old graph: (1) a 4096-point
+    segment added after a lone 2^20-point run (the old graph has no
+    work-list launch at all); (2) two lists with the same task count, hence
+    the same grid, but a different split between the two launches."""
+    import torch
+    m = 1 << 20
+    announce("work list graph key: added task after a planned run")
+    x = siggen.Signal(seed=18, seg_len=1, sigma=1.0).samples(0, m + 4096)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(m + 4096, dtype=torch.complex64, device="cuda")
+    with fs.WorkList(to_entries([0], [0], [m])) as wl:
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        check_all(x, yd.cpu().numpy(), [0], [0], [m])
+        wl.reset(to_entries([0, m], [0, m], [m, 4096]))
+        yd.zero_()
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        check_all(x, yd.cpu().numpy(), [0, m], [0, m], [m, 4096])
+
+    announce("work list graph key: same task count, other split")
+    s = 65536
+
+    def layout(n_two, n_short):
+        lengths = np.array([s] * n_two + [256] * n_short, np.int64)
+        off, total = packed(lengths)
+        return lengths, off, total
+
+    l1, o1, t1 = layout(2, 32 * 10)     # 64 two-pass + 10 one-pass tasks
+    l2, o2, t2 = layout(1, 32 * 42)     # 32 two-pass + 42 one-pass tasks
+    total = max(t1, t2)
+    x = siggen.Signal(seed=19, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(total, dtype=torch.complex64, device="cuda")
+    with fs.WorkList(to_entries(o1, o1, l1)) as wl:
+        d1 = wl.describe()
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        check_all(x, yd.cpu().numpy(), o1, o1, l1, sample=[0, 1, 2, len(l1) - 1])
+        wl.reset(to_entries(o2, o2, l2))
+        d2 = wl.describe()
+        assert d1["tasks"] == d2["tasks"] and d1["grid"] == d2["grid"]
+        assert d1["first_launch_tasks"] != d2["first_launch_tasks"]
+        yd.zero_()
+        wl.exec(xd, yd, graph=True)
+        wl.status()
+        y_graph = yd.cpu().numpy()
+        yd.zero_()
+        wl.exec(xd, yd)
+        wl.status()
+        assert np.array_equal(y_graph, yd.cpu().numpy())
+        check_all(x, y_graph, o2, o2, l2, sample=[0, 1, 500, len(l2) - 1])
+
+
+def test_one_call_worklist():
+    """fft_exec_worklist(items, n, direction, in_base, out_base, stream):
+    each call builds nothing the caller sees; two calls in a row on one
+    stream (the second list smaller), then a call on another stream, and
+    the inverse direction, all against the oracle."""
+    import torch
+    rng = np.random.default_rng(21)
+    lengths = np.array(rng.choice(LENGTHS, 40).tolist() + LENGTHS + [1 << 20], np.int64)
+    rng.shuffle(lengths)
+    in_off, total = packed(lengths, gap=1)
+    out_off, out_total = packed(lengths[::-1], gap=2)
+    out_off = out_off[::-1].copy()
+    announce("one-call work list, %d segments" % len(lengths))
+    x = siggen.Signal(seed=20, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(out_total, dtype=torch.complex64, device="cuda")
+    try:
+        fs.exec_worklist(to_entries(in_off, out_off, lengths), xd, yd)
+        torch.cuda.synchronize()
+        check_all(x, yd.cpu().numpy(), in_off, out_off, lengths)
+        k = len(lengths) // 3
+        yd.zero_()
+        fs.exec_worklist(to_entries(in_off[:k], out_off[:k], lengths[:k]), xd, yd)
+        torch.cuda.synchronize()
+        check_all(x, yd.cpu().numpy(), in_off[:k], out_off[:k], lengths[:k])
+        side = torch.cuda.Stream()
+        yd.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            fs.exec_worklist(to_entries(in_off, out_off, lengths), xd, yd, fs.INVERSE)
+        side.synchronize()
+        check_all(x, yd.cpu().numpy(), in_off, out_off, lengths, fs.INVERSE)
+        with pytest.raises(fs.FFTError) as e:
+            fs.exec_worklist(to_entries([0], [0], [7]), xd, yd)
+        assert e.value.name == "FFT_ERR_UNSUPPORTED_LENGTH"
+    finally:
+        fs.worklist_cache_clear()
