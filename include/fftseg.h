@@ -123,6 +123,25 @@ int fft_exec_segments(fft_plan_t plan, const void *in, void *out, void *stream);
 int fft_exec_segments_n(fft_plan_t plan, const void *in, void *out,
                         size_t batch, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * transform of fft_exec_segments without a plan, allocating nothing.
+ * `batch` segments of `segment_len` samples in direction FFT_FORWARD or
+ * FFT_INVERSE go from `in` to `out` (same layout, aliasing, alignment and
+ * bounds rules and the same kernels as a plan's).  The twiddle tables are
+ * computed on the device by each call, and the buffer between the two
+ * passes of long segments is used in sub-batches; both live in one static
+ * device array of the library, 2^15 + 2^24 + 32 complex64 samples (about
+ * 128 MiB) per GPU, allocated when the library's code first runs on that
+ * GPU and held until the process ends.  Supported: every length of
+ * fft_plan_create up to 2^23 (lengths without a two-pass split need two
+ * buffers of N samples); 2^24 gives FFT_ERR_UNSUPPORTED_LENGTH.  Every call
+ * on one GPU uses the same array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and give wrong results.  Asynchronous
+ * on stream. */
+int fft_exec_segments_noalloc(size_t segment_len, size_t batch, int direction,
+                              const void *in, void *out, void *stream);
+
 /* Synchronise the plan's last stream, then free the plan.  NULL is a no-op. */
 int fft_plan_destroy(fft_plan_t plan);
 

@@ -110,6 +110,7 @@ def lib():
     _sig(L, "fft_plan_create_split", vp, [sz, sz, i32, i32, i32])
     _sig(L, "fft_exec_segments", i32, [vp, vp, vp, vp])
     _sig(L, "fft_exec_segments_n", i32, [vp, vp, vp, sz, vp])
+    _sig(L, "fft_exec_segments_noalloc", i32, [sz, sz, i32, vp, vp, vp])
     _sig(L, "fft_plan_destroy", i32, [vp])
     _sig(L, "fft_last_status", i32, [])
     _sig(L, "fft_last_error", ctypes.c_char_p, [])
@@ -379,6 +380,15 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def exec_segments_noalloc_ptr(segment_len: int, batch: int, in_ptr: int, out_ptr: int,
+                              direction: int = FORWARD, stream: int = 0) -> None:
+    """fft_exec_segments_noalloc: the batched transform without a plan or
+    any device allocation (tables and scratch in the library's static
+    device array; calls overlapping on one GPU race)."""
+    _check(lib().fft_exec_segments_noalloc(segment_len, batch, direction, in_ptr, out_ptr,
+                                           stream))
 
 
 class RealPlan(Plan):

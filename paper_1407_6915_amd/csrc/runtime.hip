@@ -405,9 +405,10 @@ int env_grid_mult()
 }
 
 // ---------------------------------------------------------------------------
-// plan construction
-int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
-               int forced_split_variants, uint64_t forced_n1)
+// plan construction: the choice of kernels, split and sub-batch (host only),
+// then the device tables and scratch
+int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
+                int forced_split_variants, uint64_t forced_n1, uint64_t max_sub_samples)
 {
     p->n = n;
     p->batch = batch;
@@ -417,7 +418,6 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
         return set_error(FFT_ERR_HIP, "no HIP device available");
     }
     p->grid_mult = env_grid_mult();
-    hipError_t e;
     if (n == 1) {
         p->kind = Plan::COPY;
         return set_ok();
@@ -435,25 +435,9 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
         p->kind = Plan::SINGLE;
         if (!getenv("FFTSEG_GRID_MULT"))
             p->grid_mult = tuned_grid_mult(n, p->sp->variant, p->sp->grid_mult);
-        if ((e = upload(root_table(n), &p->tw)) != hipSuccess)
-            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
-                                            : hip_error(e, "twiddle upload");
         return set_ok();
     }
-    const uint64_t max_sub_samples = 1ull << 29;  // 4 GiB of complex64 per scratch buffer
     p->sh = ilog2_ceil(n) / 2 + (ilog2_ceil(n) & 1);
-    {
-        const uint64_t lo = 1ull << p->sh;
-        std::vector<c32> tl(lo), th((n + lo - 1) / lo);
-        for (uint64_t j = 0; j < lo; ++j)
-            tl[j] = root_forward(j, n);
-        for (uint64_t j = 0; j < th.size(); ++j)
-            th[j] = root_forward(j * lo, n);
-        if ((e = upload(tl, &p->tl)) != hipSuccess || (e = upload(th, &p->th)) != hipSuccess)
-            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
-                                            : hip_error(e, "twiddle upload");
-    }
-    p->sub_batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, max_sub_samples / n));
     int cv = 0, rv = 0;
     uint64_t n1 = forced_n1;
     if (forced_split_variants >= 0) {
@@ -476,17 +460,53 @@ int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
         p->kind = Plan::FOURSTEP;
         p->n1 = (uint64_t)p->col->n1;
         p->n2 = (uint64_t)p->row->n2;
-        if ((e = upload(root_table(p->n1), &p->tw)) != hipSuccess ||
-            (e = upload(root_table(p->n2), &p->tw2)) != hipSuccess)
-            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
-                                            : hip_error(e, "twiddle upload");
         // (one line more: Y may start at the input's offset within a line)
+        p->sub_batch = std::min<uint64_t>(batch, max_sub_samples / n);
         p->scratch_bytes = (p->sub_batch * n + kLineSamples) * sizeof(c32);
     } else {
         p->kind = Plan::GENERIC;
         p->radices = generic_radices(n);
+        p->sub_batch = std::min<uint64_t>(batch, max_sub_samples / n);
         p->scratch_bytes = 2 * p->sub_batch * n * sizeof(c32);
     }
+    if (p->sub_batch == 0)
+        return set_error(FFT_ERR_INVALID_ARG,
+                         "one %llu-point segment needs more scratch than %llu samples",
+                         (unsigned long long)n, (unsigned long long)max_sub_samples);
+    return set_ok();
+}
+
+int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
+               int forced_split_variants, uint64_t forced_n1)
+{
+    // 4 GiB of complex64 per scratch buffer (the radix-stage path has two)
+    int st = plan_choose(p, n, batch, dir, forced_variant, forced_split_variants, forced_n1,
+                         1ull << 29);
+    if (st != FFT_OK || p->kind == Plan::COPY)
+        return st;
+    hipError_t e;
+    if (p->kind == Plan::SINGLE) {
+        if ((e = upload(root_table(n), &p->tw)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+        return set_ok();
+    }
+    {
+        const uint64_t lo = 1ull << p->sh;
+        std::vector<c32> tl(lo), th((n + lo - 1) / lo);
+        for (uint64_t j = 0; j < lo; ++j)
+            tl[j] = root_forward(j, n);
+        for (uint64_t j = 0; j < th.size(); ++j)
+            th[j] = root_forward(j * lo, n);
+        if ((e = upload(tl, &p->tl)) != hipSuccess || (e = upload(th, &p->th)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                            : hip_error(e, "twiddle upload");
+    }
+    if (p->kind == Plan::FOURSTEP &&
+        ((e = upload(root_table(p->n1), &p->tw)) != hipSuccess ||
+         (e = upload(root_table(p->n2), &p->tw2)) != hipSuccess))
+        return e == hipErrorOutOfMemory ? set_error(FFT_ERR_OUT_OF_MEMORY, "twiddles")
+                                        : hip_error(e, "twiddle upload");
     e = hipMalloc(&p->scratch, p->scratch_bytes);
     if (e != hipSuccess) {
         p->scratch = nullptr;

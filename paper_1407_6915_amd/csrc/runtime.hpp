@@ -81,6 +81,11 @@ int validate_create(uint64_t n, uint64_t batch, int dir);
 // forced_n1: column length of a four-step plan (0: tuned/default)
 int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
                int forced_split_variants = -1, uint64_t forced_n1 = 0);
+// the kernels, split and sub-batch of a plan (host only: no device memory);
+// a sub-batch fills at most max_sub_samples samples of each scratch buffer
+// (two-pass plans have one, the radix-stage path two)
+int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
+                int forced_split_variants, uint64_t forced_n1, uint64_t max_sub_samples);
 void plan_free(Plan *p);
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s);
 // real-input plans: length n = 2m through the m-point one-pass kernel, or,
