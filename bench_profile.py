@@ -11,6 +11,11 @@ under profiles/.
            reads for the plain device copy of a known size in the same run
            (bench.py --copy-reference copies samples*8 bytes each way)
 
+  overlap  <kernel_trace.csv> <memory_copy_trace.csv> <out.md> <chunks> <command...>
+           per-chunk host-to-device copy, transform and device-to-host copy
+           intervals of the streamed runs (bench.py --workload streamed), and
+           how much of the time copies and transforms overlap
+
 The traffic file records the hash of the device sources it was measured
 on; bench.py reports it only while the sources are unchanged.
 """
@@ -97,10 +102,124 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, samples: int,
     print(json.dumps(out))
 
 
+def _col(row, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    raise KeyError("none of %s in %s" % (names, sorted(row)))
+
+
+def _union(iv):
+    """Total length covered by a list of (start, end) intervals."""
+    tot, cur_s, cur_e = 0.0, None, None
+    for a, b in sorted(iv):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot
+
+
+def _covered(iv, by):
+    """Length of the intervals iv that lies inside the union of `by`."""
+    tot = 0.0
+    merged = []
+    for a, b in sorted(by):
+        if merged and a <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], b)
+        else:
+            merged.append([a, b])
+    for a, b in iv:
+        for c, d in merged:
+            lo, hi = max(a, c), min(b, d)
+            if hi > lo:
+                tot += hi - lo
+    return tot
+
+
+def overlap(kernel_csv: str, copy_csv: str, out_md: str, chunks: int, command: str) -> None:
+    kern = []
+    for r in csv.DictReader(open(kernel_csv)):
+        name = _col(r, "Kernel_Name")
+        if "four_step" in name:
+            kern.append((int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp")), name))
+    h2d, d2h = [], []
+    for r in csv.DictReader(open(copy_csv)):
+        a, b = int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp"))
+        direction = _col(r, "Direction", "Operation", "Kind").upper()
+        if b - a < 5_000_000:          # the chunk copies take tens of ms; skip small ones
+            continue
+        if "HOST_TO_DEVICE" in direction:
+            h2d.append((a, b))
+        elif "DEVICE_TO_HOST" in direction:
+            d2h.append((a, b))
+    h2d.sort()
+    d2h.sort()
+    kern.sort()
+    runs = len(h2d) // chunks
+    if runs == 0 or len(d2h) < runs * chunks:
+        raise SystemExit("expected %d-chunk runs, got %d H2D and %d D2H chunk copies"
+                         % (chunks, len(h2d), len(d2h)))
+    names = ["pool of pre-generated pinned chunks (link reference)",
+             "every chunk generated from the seed (as configured)"]
+    lines = ["# Streamed 2^20-point chunks: copy/compute overlap", "",
+             "Command (run from the repository root):", "", "    " + command, "",
+             "Chunks of 512 segments (4 GiB each way). Intervals from the rocprofv3 kernel "
+             "trace (the four-step column and row kernels of each chunk) and memory-copy "
+             "trace (copies of 5 ms or more: the chunk copies), in ms from the run's "
+             "first copy.", ""]
+    for r in range(runs):
+        H = h2d[r * chunks:(r + 1) * chunks]
+        D = d2h[r * chunks:(r + 1) * chunks]
+        t0, t1 = H[0][0], D[-1][1]
+        K = [(a, b) for a, b, _ in kern if a >= t0 and b <= t1]
+        per = [[(a, b) for a, b in K if a >= H[c][1] and b <= D[c][0]] for c in range(chunks)]
+        busy = [(a, b) for a, b in H + D + K]
+        copies = H + D
+        wall = t1 - t0
+        sum_h = sum(b - a for a, b in H)
+        sum_d = sum(b - a for a, b in D)
+        sum_k = sum(b - a for a, b in K)
+        k_under_copy = _covered(K, copies)
+        h_under_d = _covered(H, D)
+        lines += ["## Run %d: %s" % (r + 1, names[r] if r < len(names) else "run %d" % (r + 1)),
+                  "",
+                  "| chunk | H2D start–end | transform start–end | D2H start–end |",
+                  "|---|---|---|---|"]
+        ms = lambda t: (t - t0) / 1e6  # noqa: E731
+        for c in range(chunks):
+            kc = per[c]
+            ks = "%.1f–%.1f" % (ms(kc[0][0]), ms(kc[-1][1])) if kc else "—"
+            lines.append("| %d | %.1f–%.1f | %s | %.1f–%.1f |" % (
+                c, ms(H[c][0]), ms(H[c][1]), ks, ms(D[c][0]), ms(D[c][1])))
+        lines += ["",
+                  "* wall (first H2D start to last D2H end): %.1f ms" % (wall / 1e6),
+                  "* H2D busy %.1f ms (%.1f GB/s per copy), D2H busy %.1f ms (%.1f GB/s per "
+                  "copy), transforms %.1f ms" % (
+                      sum_h / 1e6, chunks * 4 * 2 ** 30 / sum_h, sum_d / 1e6,
+                      chunks * 4 * 2 ** 30 / sum_d, sum_k / 1e6),
+                  "* sum of busy intervals / wall: %.2f (1.0 would mean no overlap)" % (
+                      (sum_h + sum_d + sum_k) / wall),
+                  "* device idle (no copy and no transform): %.1f ms of %.1f" % (
+                      (wall - _union(busy)) / 1e6, wall / 1e6),
+                  "* transform time with a copy in flight: %.1f %%" % (
+                      100.0 * k_under_copy / max(sum_k, 1)),
+                  "* H2D time with a D2H in flight: %.1f %%" % (100.0 * h_under_d / max(sum_h, 1)),
+                  ""]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         kernels(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6:8])
+    elif sys.argv[1] == "overlap":
+        overlap(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), " ".join(sys.argv[6:]))
     else:
         raise SystemExit(__doc__)

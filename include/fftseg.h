@@ -213,6 +213,17 @@ int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
                            void *const *host_out, int n_out, int n_slots,
                            fft_stream_stats_t *stats);
 
+/* Pinned (page-locked) host memory for fft_exec_stream_pinned, for callers
+ * with no pinned allocator of their own (Sec. III's large host transfers
+ * run at the link's full rate only from pinned memory).  fft_host_alloc
+ * returns NULL on failure (bytes == 0 -> FFT_ERR_INVALID_ARG, allocation
+ * failure -> FFT_ERR_OUT_OF_MEMORY; fft_last_error says why).  The caller
+ * owns the memory and releases it with fft_host_free before the process
+ * ends: no library destructor frees it.  fft_host_free(NULL) is a no-op;
+ * a pointer not from fft_host_alloc -> FFT_ERR_HIP. */
+void *fft_host_alloc(size_t bytes);
+int fft_host_free(void *ptr);
+
 /* Overlapping, optionally windowed segments: a short-time transform, the
  * overlapping FFTs named as future work in Sec. VI.  Frame s
  * (0 <= s < n_frames) is

@@ -122,6 +122,8 @@ def lib():
     _sig(L, "fft_exec_stream_pinned", i32, [vp, u64, ctypes.POINTER(vp), i32,
                                             ctypes.POINTER(vp), i32, i32,
                                             ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_host_alloc", vp, [sz])
+    _sig(L, "fft_host_free", i32, [vp])
     _sig(L, "fft_exec_file", i32, [vp, ctypes.c_char_p, u64, ctypes.c_char_p, u64, u64, u64,
                                    i32, i32, ctypes.POINTER(u64), ctypes.POINTER(StreamStats)])
     _sig(L, "fft_exec_frames", i32, [vp, vp, sz, vp, sz, sz, vp, vp])
@@ -572,3 +574,32 @@ def tune_load(path: str) -> int:
 
 def tune_clear() -> None:
     _check(lib().fft_tune_clear())
+
+
+class HostBuffer:
+    """Pinned host memory from fft_host_alloc, freed by close() (or the
+    context manager); ``ptr`` is its address."""
+
+    def __init__(self, nbytes: int):
+        p = lib().fft_host_alloc(nbytes)
+        if not p:
+            raise FFTError(lib().fft_last_status(), last_error())
+        self.ptr = int(p)
+        self.nbytes = int(nbytes)
+
+    def view(self, dtype="complex64"):
+        """numpy view of the buffer (valid until close)."""
+        import numpy as np
+        buf = (ctypes.c_char * self.nbytes).from_address(self.ptr)
+        return np.frombuffer(buf, dtype=dtype)
+
+    def close(self) -> None:
+        if getattr(self, "ptr", 0):
+            _check(lib().fft_host_free(self.ptr))
+            self.ptr = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -499,3 +499,30 @@ extern "C" int fft_exec_file(fft_plan_t plan, const char *in_path, uint64_t in_o
         return set_error(code, "%s", msg.c_str());
     return set_ok();
 }
+
+extern "C" void *fft_host_alloc(size_t bytes)
+{
+    if (bytes == 0) {
+        set_error(FFT_ERR_INVALID_ARG, "fft_host_alloc: 0 bytes");
+        return nullptr;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(FFT_ERR_OUT_OF_MEMORY, "pinned host allocation of %llu bytes",
+                  (unsigned long long)bytes);
+        return nullptr;
+    }
+    set_ok();
+    return p;
+}
+
+extern "C" int fft_host_free(void *ptr)
+{
+    if (!ptr)
+        return set_ok();
+    hipError_t e = hipHostFree(ptr);
+    if (e != hipSuccess)
+        return hip_error(e, "hipHostFree");
+    return set_ok();
+}

@@ -25,12 +25,15 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``siggen.c`` with gcc (-O2, OpenMP)."""
+    """Compile ``siggen.c`` with gcc (-O3, OpenMP, no floating-point
+    contraction, so that every instruction-set clone gives the same bits)."""
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+           "-fno-fast-math", "-ffp-contract=off", "-fno-math-errno",
+           "-fno-trapping-math",
+           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -56,6 +59,11 @@ class _CChunkSource(ctypes.Structure):
         ("first_sample", ctypes.c_uint64),
         ("chunk_samples", ctypes.c_uint64),
         ("threads", ctypes.c_int),
+        ("check_seg_len", ctypes.c_uint64),
+        ("n_chunks", ctypes.c_uint64),
+        ("energy_in", ctypes.c_void_p),
+        ("energy_out", ctypes.c_void_p),
+        ("saved_out", ctypes.c_void_p),
     ]
 
 
@@ -77,9 +85,24 @@ def _load():
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                       ctypes.c_uint64, ctypes.c_void_p]
-    lib.sg_fill_chunk.restype = ctypes.c_int
-    lib.sg_fill_chunk.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
-                                  ctypes.c_void_p, ctypes.c_uint64]
+    lib.sg_fill_segments.restype = ctypes.c_int
+    lib.sg_fill_segments.argtypes = [ctypes.POINTER(_CSignal), ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int]
+    lib.sg_energy.restype = ctypes.c_int
+    lib.sg_energy.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                              ctypes.c_void_p, ctypes.c_int]
+    for name in ("sg_fill_chunk", "sg_drain_chunk"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                      ctypes.c_uint64]
+    lib.sg_set_isa.restype = ctypes.c_int
+    lib.sg_set_isa.argtypes = [ctypes.c_int]
+    lib.sg_test_ln.restype = ctypes.c_double
+    lib.sg_test_ln.argtypes = [ctypes.c_double]
+    lib.sg_test_turn.restype = None
+    lib.sg_test_turn.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -157,6 +180,21 @@ class Signal:
         n = self.seg_len
         return self.samples(first_seg * n, n_seg * n, threads).reshape(n_seg, n)
 
+    def segments_with_energy(self, first_seg: int, n_seg: int, threads: int = 0):
+        """(segments as complex64 [n_seg, seg_len], each segment's energy
+        sum |x|^2 of the stored float32 values in float64)."""
+        n = self.seg_len
+        out = np.empty((n_seg, n), dtype=np.complex64)
+        e = np.empty(n_seg, dtype=np.float64)
+        if n_seg:
+            cs, keep = self._c()
+            rc = _load().sg_fill_segments(ctypes.byref(cs), first_seg, n_seg,
+                                          out.ctypes.data, e.ctypes.data, threads)
+            del keep
+            if rc != 0:
+                raise RuntimeError("sg_fill_segments failed (%d)" % rc)
+        return out, e
+
     def chunk_source(self, first_sample: int, chunk_samples: int,
                      threads: int = 0):
         """(callback address, user struct) for a native chunk producer of
@@ -168,6 +206,72 @@ class Signal:
         src._keep = keep  # arrays referenced by the struct
         addr = ctypes.cast(_load().sg_fill_chunk, ctypes.c_void_p).value
         return addr, src
+
+    def checked_chunk_source(self, chunk_segments: int, n_chunks: int,
+                             first_seg: int = 0, threads: int = 0):
+        """Producer and consumer for streaming n_chunks chunks of
+        chunk_segments whole segments (chunk c = segments first_seg +
+        c*chunk_segments ..).  The producer records every segment's input
+        energy, the consumer every segment's output energy and a copy of the
+        first and last segment of each chunk.  Returns (fill address, drain
+        address, user struct, CheckedStream with the arrays)."""
+        n = self.seg_len
+        chk = CheckedStream(
+            energy_in=np.zeros((n_chunks, chunk_segments), np.float64),
+            energy_out=np.zeros((n_chunks, chunk_segments), np.float64),
+            saved_out=np.zeros((n_chunks, 2, n), np.complex64))
+        cs, keep = self._c()
+        src = _CChunkSource(cs, first_seg * n, chunk_segments * n, threads, n,
+                            n_chunks, chk.energy_in.ctypes.data,
+                            chk.energy_out.ctypes.data, chk.saved_out.ctypes.data)
+        src._keep = (keep, chk)
+        L = _load()
+        fill = ctypes.cast(L.sg_fill_chunk, ctypes.c_void_p).value
+        drain = ctypes.cast(L.sg_drain_chunk, ctypes.c_void_p).value
+        return fill, drain, src, chk
+
+
+@dataclass
+class CheckedStream:
+    """Per-segment energies ([chunk, segment]) of a checked streamed run and
+    the first and last output segment of every chunk ([chunk, 2, seg_len])."""
+    energy_in: np.ndarray
+    energy_out: np.ndarray
+    saved_out: np.ndarray
+
+
+def segment_energy(x: np.ndarray, threads: int = 0) -> np.ndarray:
+    """Energy sum |x|^2 in float64 of each row of a complex64 [n_seg, n]
+    array."""
+    a = np.ascontiguousarray(x, dtype=np.complex64)
+    if a.ndim == 1:
+        a = a[None]
+    out = np.empty(a.shape[0], dtype=np.float64)
+    if a.shape[0]:
+        rc = _load().sg_energy(a.ctypes.data, a.shape[0], a.shape[1], out.ctypes.data,
+                               threads)
+        if rc != 0:
+            raise RuntimeError("sg_energy failed (%d)" % rc)
+    return out
+
+
+def set_isa(cap: int) -> int:
+    """Cap the generator's instruction-set version (0 baseline x86-64, 1
+    AVX2 + FMA, 2 AVX-512); returns the version then in use.  Every version
+    computes the same bits."""
+    return int(_load().sg_set_isa(cap))
+
+
+def _test_ln(x: float) -> float:
+    """The generator's own natural log (for its tests)."""
+    return float(_load().sg_test_ln(x))
+
+
+def _test_turn(num: int, den: int):
+    """The generator's own (cos, sin)(2 pi num / den) (for its tests)."""
+    o = (ctypes.c_double * 2)()
+    _load().sg_test_turn(num, den, o)
+    return float(o[0]), float(o[1])
 
 
 def distinct_bins(seed: int, stream: int, n: int, count: int) -> List[int]:

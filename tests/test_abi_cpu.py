@@ -57,6 +57,13 @@ def test_null_plan_calls():
     assert L.fft_plan_scratch_bytes(None) == 0
 
 
+def test_host_alloc_argument_checks():
+    L = fs.lib()
+    assert not L.fft_host_alloc(0)
+    assert L.fft_last_status() == -1 and fs.last_error()
+    assert L.fft_host_free(None) == 0
+
+
 def test_factorize_matches_lengths():
     for n in (2, 16, 256, 1000, 1024, 1536, 4096, 6000, 16384, 65536, 3 ** 9,
               2 * 3 * 5 * 7 * 0 + 30, 1 << 20):

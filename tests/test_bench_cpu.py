@@ -59,3 +59,39 @@ def test_traffic_is_reported_only_for_the_measured_kernel(tmp_path, monkeypatch)
     rec["kernel_source_hash"] = "0" * 16                  # another kernel
     p.write_text(json.dumps(rec))
     assert bench.measured_traffic(4096) is None
+
+
+def test_overlap_summary_from_traces(tmp_path):
+    """Two chunks: H2D 0-10 / 10-20 ms, transforms 10-14 / 20-24, D2H
+    14-24 / 24-34 (ms); small copies are ignored."""
+    ms = 1_000_000
+    kp, cp = tmp_path / "k.csv", tmp_path / "c.csv"
+    with open(kp, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for a, b in [(10, 12), (12, 14), (20, 22), (22, 24)]:
+            w.writerow({"Kernel_Name": "four_step_columns_kernel<...>",
+                        "Start_Timestamp": a * ms, "End_Timestamp": b * ms})
+        w.writerow({"Kernel_Name": "other", "Start_Timestamp": 0, "End_Timestamp": 50 * ms})
+    with open(cp, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Direction", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        rows = [("MEMORY_COPY_HOST_TO_DEVICE", 0, 10), ("MEMORY_COPY_HOST_TO_DEVICE", 10, 20),
+                ("MEMORY_COPY_DEVICE_TO_HOST", 14, 24), ("MEMORY_COPY_DEVICE_TO_HOST", 24, 34)]
+        for d, a, b in rows:
+            w.writerow({"Direction": d, "Start_Timestamp": a * ms, "End_Timestamp": b * ms})
+        w.writerow({"Direction": "MEMORY_COPY_HOST_TO_DEVICE", "Start_Timestamp": 40 * ms,
+                    "End_Timestamp": 40 * ms + 1000})
+    out = tmp_path / "o.md"
+    bench_profile.overlap(str(kp), str(cp), str(out), 2, "cmd")
+    text = out.read_text()
+    assert "| 0 | 0.0–10.0 | 10.0–14.0 | 14.0–24.0 |" in text
+    assert "| 1 | 10.0–20.0 | 20.0–24.0 | 24.0–34.0 |" in text
+    assert "wall (first H2D start to last D2H end): 34.0 ms" in text
+    # busy 20 + 20 + 8 = 48 ms over 34 ms of wall
+    assert "sum of busy intervals / wall: 1.41" in text
+    # transforms 10-14 (H2D 10-20 in flight) and 20-24 (D2H 14-24 in flight)
+    assert "transform time with a copy in flight: 100.0 %" in text
+    # H2D 10-20 overlaps D2H 14-24 for 6 of the 20 ms
+    assert "H2D time with a D2H in flight: 30.0 %" in text
+    assert "device idle (no copy and no transform): 0.0 ms" in text

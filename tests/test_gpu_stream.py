@@ -111,3 +111,50 @@ def test_stream_pinned_buffers():
         x = ins[c].numpy().reshape(batch, n)
         y = outs[c].numpy().reshape(batch, n)
         assert np.all(oracle.rel_l2(y, oracle.fft_recursive(x, n)) <= oracle.tolerance(n))
+
+
+def test_stream_configured_long_shape_every_segment():
+    """The streamed 2^20-point workload at its configured chunk shape (512
+    segments, 4 GiB per chunk), 3 chunks generated from the seed by the
+    native producer: Parseval on every one of the 1536 segments and the
+    oracle on the first and last segment of each chunk."""
+    from siggen import workloads
+    n, seg, chunks = workloads.LONG["seg_len"], workloads.LONG["chunk_segments"], 3
+    announce("stream configured 2^20 x 512 per chunk, %d chunks" % chunks)
+    sig = workloads.long_signal()
+    fill, drain, src, chk = sig.checked_chunk_source(seg, chunks)
+    with fs.Plan(n, seg) as plan:
+        rc, failed, st = plan.exec_stream(chunks, (fill, src), (drain, src), 3)
+    assert rc == 0 and failed is None and st["chunks_done"] == chunks
+    tol = oracle.tolerance(n)
+    dev = np.abs(chk.energy_out / (n * chk.energy_in) - 1.0)
+    print("  parseval max rel dev %.3e over %d segments" % (dev.max(), dev.size), flush=True)
+    assert dev.size == chunks * seg and np.all(dev <= 2 * tol + tol * tol)
+    # the kept first and last segments, against the oracle
+    idx = [c * seg + s for c in range(chunks) for s in (0, seg - 1)]
+    x = np.concatenate([sig.segments(i, 1) for i in idx])
+    err = oracle.rel_l2(chk.saved_out.reshape(-1, n), oracle.fft_recursive(x, n))
+    print("  oracle max rel-L2 %.3e on %d segments" % (err.max(), len(idx)), flush=True)
+    assert np.all(err <= tol)
+
+
+def test_stream_library_pinned_buffers():
+    n, batch, chunks, pool = 1 << 16, 8, 5, 2
+    announce("stream library pinned buffers")
+    sig = siggen.Signal(seed=8, seg_len=n, sigma=1.0, chirp_amp=0.5)
+    nbytes = batch * n * 8
+    ins = [fs.HostBuffer(nbytes) for _ in range(pool)]
+    outs = [fs.HostBuffer(nbytes) for _ in range(pool)]
+    try:
+        for c in range(pool):
+            sig.fill_ptr(c * batch * n, batch * n, ins[c].ptr)
+        with fs.Plan(n, batch) as plan:
+            st = plan.exec_stream_pinned(chunks, [b.ptr for b in ins], [b.ptr for b in outs], 3)
+        assert st["chunks_done"] == chunks
+        for c in range(pool):
+            x = ins[c].view().reshape(batch, n).copy()
+            y = outs[c].view().reshape(batch, n).copy()
+            assert np.all(oracle.rel_l2(y, oracle.fft_recursive(x, n)) <= oracle.tolerance(n))
+    finally:
+        for b in ins + outs:
+            b.close()
