@@ -218,6 +218,8 @@ def main():
                     help="large = the 4096-point x 262144 batch (the reported metric); "
                          "the others print their own JSON line")
     ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")
+    ap.add_argument("--overlap-md", default="",
+                    help="streamed: write the per-chunk copy/transform timeline here")
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per rate")
     ap.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.0,1.2,1.5,2.0",
                     help="serving: arrival rates as fractions of the plain path's saturation")

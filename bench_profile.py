@@ -141,6 +141,64 @@ def _covered(iv, by):
     return tot
 
 
+def overlap_stats(H, K, D):
+    """Overlap figures of one streamed run from its chunk intervals: H (copy
+    in), K (transforms), D (copy out), each a list of (start, end) in ns."""
+    t0, t1 = min(a for a, _ in H), max(b for _, b in D)
+    wall = t1 - t0
+    sum_h = sum(b - a for a, b in H)
+    sum_d = sum(b - a for a, b in D)
+    sum_k = sum(b - a for a, b in K)
+    return {"wall_ms": wall / 1e6, "h2d_busy_ms": sum_h / 1e6, "d2h_busy_ms": sum_d / 1e6,
+            "transform_busy_ms": sum_k / 1e6,
+            "busy_over_wall": (sum_h + sum_d + sum_k) / wall,
+            "device_idle_ms": (wall - _union(H + D + K)) / 1e6,
+            "transform_with_copy_in_flight": _covered(K, H + D) / max(sum_k, 1),
+            "h2d_with_d2h_in_flight": _covered(H, D) / max(sum_h, 1)}
+
+
+def overlap_lines(title, H, K_per_chunk, D, chunk_bytes):
+    """Markdown table and figures of one run (intervals in ns)."""
+    K = [iv for ks in K_per_chunk for iv in ks]
+    st = overlap_stats(H, K, D)
+    t0 = min(a for a, _ in H)
+    ms = lambda t: (t - t0) / 1e6  # noqa: E731
+    lines = ["## " + title, "",
+             "| chunk | H2D start–end | transform start–end | D2H start–end |",
+             "|---|---|---|---|"]
+    for c in range(len(H)):
+        kc = K_per_chunk[c]
+        ks = "%.1f–%.1f" % (ms(kc[0][0]), ms(kc[-1][1])) if kc else "—"
+        lines.append("| %d | %.1f–%.1f | %s | %.1f–%.1f |" % (
+            c, ms(H[c][0]), ms(H[c][1]), ks, ms(D[c][0]), ms(D[c][1])))
+    n = len(H)
+    lines += ["",
+              "* wall (first H2D start to last D2H end): %.1f ms" % st["wall_ms"],
+              "* H2D busy %.1f ms (%.1f GB/s per copy), D2H busy %.1f ms (%.1f GB/s per "
+              "copy), transforms %.1f ms" % (
+                  st["h2d_busy_ms"], n * chunk_bytes / st["h2d_busy_ms"] / 1e6,
+                  st["d2h_busy_ms"], n * chunk_bytes / st["d2h_busy_ms"] / 1e6,
+                  st["transform_busy_ms"]),
+              "* sum of busy intervals / wall: %.2f (1.0 would mean no overlap)"
+              % st["busy_over_wall"],
+              "* device idle (no copy and no transform): %.1f ms of %.1f" % (
+                  st["device_idle_ms"], st["wall_ms"]),
+              "* transform time with a copy in flight: %.1f %%" % (
+                  100.0 * st["transform_with_copy_in_flight"]),
+              "* H2D time with a D2H in flight: %.1f %%" % (100.0 * st["h2d_with_d2h_in_flight"]),
+              ""]
+    return lines
+
+
+def timeline_intervals(timeline):
+    """(H, K per chunk, D) in ns from fft_stream_last_timeline entries."""
+    ns = lambda v: int(round(v * 1e6))  # noqa: E731
+    H = [(ns(t["h2d_start_ms"]), ns(t["h2d_end_ms"])) for t in timeline]
+    K = [[(ns(t["compute_start_ms"]), ns(t["compute_end_ms"]))] for t in timeline]
+    D = [(ns(t["d2h_start_ms"]), ns(t["d2h_end_ms"])) for t in timeline]
+    return H, K, D
+
+
 def overlap(kernel_csv: str, copy_csv: str, out_md: str, chunks: int, command: str) -> None:
     kern = []
     for r in csv.DictReader(open(kernel_csv)):
@@ -178,38 +236,8 @@ def overlap(kernel_csv: str, copy_csv: str, out_md: str, chunks: int, command: s
         t0, t1 = H[0][0], D[-1][1]
         K = [(a, b) for a, b, _ in kern if a >= t0 and b <= t1]
         per = [[(a, b) for a, b in K if a >= H[c][1] and b <= D[c][0]] for c in range(chunks)]
-        busy = [(a, b) for a, b in H + D + K]
-        copies = H + D
-        wall = t1 - t0
-        sum_h = sum(b - a for a, b in H)
-        sum_d = sum(b - a for a, b in D)
-        sum_k = sum(b - a for a, b in K)
-        k_under_copy = _covered(K, copies)
-        h_under_d = _covered(H, D)
-        lines += ["## Run %d: %s" % (r + 1, names[r] if r < len(names) else "run %d" % (r + 1)),
-                  "",
-                  "| chunk | H2D start–end | transform start–end | D2H start–end |",
-                  "|---|---|---|---|"]
-        ms = lambda t: (t - t0) / 1e6  # noqa: E731
-        for c in range(chunks):
-            kc = per[c]
-            ks = "%.1f–%.1f" % (ms(kc[0][0]), ms(kc[-1][1])) if kc else "—"
-            lines.append("| %d | %.1f–%.1f | %s | %.1f–%.1f |" % (
-                c, ms(H[c][0]), ms(H[c][1]), ks, ms(D[c][0]), ms(D[c][1])))
-        lines += ["",
-                  "* wall (first H2D start to last D2H end): %.1f ms" % (wall / 1e6),
-                  "* H2D busy %.1f ms (%.1f GB/s per copy), D2H busy %.1f ms (%.1f GB/s per "
-                  "copy), transforms %.1f ms" % (
-                      sum_h / 1e6, chunks * 4 * 2 ** 30 / sum_h, sum_d / 1e6,
-                      chunks * 4 * 2 ** 30 / sum_d, sum_k / 1e6),
-                  "* sum of busy intervals / wall: %.2f (1.0 would mean no overlap)" % (
-                      (sum_h + sum_d + sum_k) / wall),
-                  "* device idle (no copy and no transform): %.1f ms of %.1f" % (
-                      (wall - _union(busy)) / 1e6, wall / 1e6),
-                  "* transform time with a copy in flight: %.1f %%" % (
-                      100.0 * k_under_copy / max(sum_k, 1)),
-                  "* H2D time with a D2H in flight: %.1f %%" % (100.0 * h_under_d / max(sum_h, 1)),
-                  ""]
+        title = "Run %d: %s" % (r + 1, names[r] if r < len(names) else "run %d" % (r + 1))
+        lines += overlap_lines(title, H, per, D, 4 * 2 ** 30)
     open(out_md, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

@@ -151,6 +151,7 @@ def streamed(args):
         sig.fill_ptr(c * chunk_samples, chunk_samples, ins[c].ptr)
     t_pool = time.perf_counter() - t0
     st = plan.exec_stream_pinned(chunks, [b.ptr for b in ins], [b.ptr for b in outs], 3)
+    tl_pool = plan.stream_timeline()
     # Parseval on the pool's last round of outputs
     from siggen import segment_energy
     pool_dev = 0.0
@@ -165,6 +166,7 @@ def streamed(args):
     # (2) as configured: generated from the seed, every segment checked
     fill, drain, src, chk = sig.checked_chunk_source(seg, chunks)
     rc, failed, stg = plan.exec_stream(chunks, (fill, src), (drain, src), 3)
+    tl_gen = plan.stream_timeline()
     plan.close()
     if rc != 0:
         raise RuntimeError("streamed run failed at chunk %s (status %d)" % (failed, rc))
@@ -179,6 +181,26 @@ def streamed(args):
     t_oracle = time.perf_counter() - t0
     errs = oracle.rel_l2(chk.saved_out.reshape(-1, n), ref)
     del xs, ref
+
+    import bench_profile
+    overlap = {}
+    md = ["# Streamed 2^20-point chunks: copy/compute overlap", "",
+          "Command (run from the repository root):", "",
+          "    python3 bench.py --workload streamed --chunks %d --overlap-md %s"
+          % (chunks, args.overlap_md), "",
+          "Chunks of 512 segments (4 GiB each way).  Intervals from the pipeline's HIP events "
+          "on its three streams (copy in, transform, copy out), read back on the GPU clock "
+          "with fft_stream_last_timeline, in ms from chunk 0's copy-in start.", ""]
+    for key, title, tl in (("link_reference", "Pool of pre-generated pinned chunks "
+                            "(link reference)", tl_pool),
+                           ("as_configured", "Every chunk generated from the seed "
+                            "(as configured)", tl_gen)):
+        H, K, D = bench_profile.timeline_intervals(tl)
+        overlap[key] = {k: round(v, 4) for k, v in
+                        bench_profile.overlap_stats(H, [iv for ks in K for iv in ks], D).items()}
+        md += bench_profile.overlap_lines(title, H, K, D, nbytes)
+    if args.overlap_md:
+        open(args.overlap_md, "w").write("\n".join(md) + "\n")
 
     link_wall = st["wall_s"]
     gen_wall = stg["wall_s"]
@@ -199,7 +221,8 @@ def streamed(args):
                "h2d_s": round(stg["h2d_s"], 3), "d2h_s": round(stg["d2h_s"], 3),
                "transform_s": round(stg["compute_s"], 3),
                "bound_by": ("host generation and checks" if host_s > 0.8 * gen_wall and
-                            gen_wall > 1.2 * link_wall else "host link")},
+                            gen_wall > 1.2 * link_wall else "host link"),
+               "overlap": overlap["as_configured"]},
            "link_reference": {
                "input": "%d pre-generated pinned chunks cycled" % pool,
                "wall_s": round(link_wall, 3),
@@ -215,7 +238,8 @@ def streamed(args):
                "amdahl_parallel_fraction": round(st["compute_s"] /
                                                  (st["compute_s"] + st["h2d_s"]), 4),
                "pool_fill_s": round(t_pool, 2),
-               "parseval_max_rel_dev_last_round": pool_dev},
+               "parseval_max_rel_dev_last_round": pool_dev,
+               "overlap": overlap["link_reference"]},
            "checks": {
                "parseval_segments": int(dev.size),
                "parseval_max_rel_dev": float(dev.max()),

@@ -213,6 +213,25 @@ int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
                            void *const *host_out, int n_out, int n_slots,
                            fft_stream_stats_t *stats);
 
+/* Per-chunk timeline of a streamed call, on the GPU clock, in ms from the
+ * start of chunk 0's host->device copy: when each chunk's copy in, its
+ * transform and its copy out started and ended.  It is how the overlap of
+ * copies and transforms (Sec. III's concern that host transfers dominate)
+ * is measured from inside the pipeline. */
+typedef struct {
+    uint64_t chunk;
+    float h2d_start_ms, h2d_end_ms;
+    float compute_start_ms, compute_end_ms;
+    float d2h_start_ms, d2h_end_ms;
+} fft_chunk_times_t;
+
+/* Copy up to `max` entries of the timeline of the plan's last
+ * fft_exec_stream, fft_exec_stream_pinned or fft_exec_file call (one per
+ * chunk that completed, in chunk order) into out; returns the number of
+ * entries the timeline holds (0 before any streamed call).  NULL plan, or
+ * NULL out with max > 0 -> FFT_ERR_INVALID_ARG. */
+int fft_stream_last_timeline(fft_plan_t plan, fft_chunk_times_t *out, size_t max);
+
 /* Pinned (page-locked) host memory for fft_exec_stream_pinned, for callers
  * with no pinned allocator of their own (Sec. III's large host transfers
  * run at the link's full rate only from pinned memory).  fft_host_alloc

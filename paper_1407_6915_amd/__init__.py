@@ -62,6 +62,15 @@ FILL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
 DRAIN_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
                             ctypes.c_void_p, ctypes.c_uint64)
 
+class ChunkTimes(ctypes.Structure):
+    """fft_chunk_times_t: one chunk's copy-in, transform and copy-out
+    intervals on the GPU clock (ms from chunk 0's copy-in start)."""
+    _fields_ = [("chunk", ctypes.c_uint64),
+                ("h2d_start_ms", ctypes.c_float), ("h2d_end_ms", ctypes.c_float),
+                ("compute_start_ms", ctypes.c_float), ("compute_end_ms", ctypes.c_float),
+                ("d2h_start_ms", ctypes.c_float), ("d2h_end_ms", ctypes.c_float)]
+
+
 class WorkItem(ctypes.Structure):
     """fft_work_t: sample offsets of one segment and of its spectrum."""
     _fields_ = [("in_off", ctypes.c_uint64), ("out_off", ctypes.c_uint64),
@@ -122,6 +131,7 @@ def lib():
     _sig(L, "fft_exec_stream_pinned", i32, [vp, u64, ctypes.POINTER(vp), i32,
                                             ctypes.POINTER(vp), i32, i32,
                                             ctypes.POINTER(StreamStats)])
+    _sig(L, "fft_stream_last_timeline", i32, [vp, ctypes.POINTER(ChunkTimes), sz])
     _sig(L, "fft_host_alloc", vp, [sz])
     _sig(L, "fft_host_free", i32, [vp])
     _sig(L, "fft_exec_file", i32, [vp, ctypes.c_char_p, u64, ctypes.c_char_p, u64, u64, u64,
@@ -355,6 +365,15 @@ class Plan:
                                             ctypes.byref(st)))
         return st.as_dict()
 
+    def stream_timeline(self) -> List[dict]:
+        """Per-chunk copy and transform intervals of the last streamed call
+        (ms on the GPU clock from chunk 0's copy-in start)."""
+        L = lib()
+        n = _check(L.fft_stream_last_timeline(self.handle, None, 0))
+        arr = (ChunkTimes * max(n, 1))()
+        _check(L.fft_stream_last_timeline(self.handle, arr, n))
+        return [{f: getattr(arr[i], f) for f, _ in ChunkTimes._fields_} for i in range(n)]
+
     def describe(self) -> dict:
         L = lib()
         need = _check(L.fft_plan_describe(self.handle, None, 0))
@@ -508,6 +527,15 @@ class WorkList:
     def status(self, stream=None) -> None:
         """Synchronise and raise FFTError if the last run did not complete."""
         _check(lib().fft_worklist_status(self.handle, _stream_handle(stream)))
+
+    def stream_timeline(self) -> List[dict]:
+        """Per-chunk copy and transform intervals of the last streamed call
+        (ms on the GPU clock from chunk 0's copy-in start)."""
+        L = lib()
+        n = _check(L.fft_stream_last_timeline(self.handle, None, 0))
+        arr = (ChunkTimes * max(n, 1))()
+        _check(L.fft_stream_last_timeline(self.handle, arr, n))
+        return [{f: getattr(arr[i], f) for f, _ in ChunkTimes._fields_} for i in range(n)]
 
     def describe(self) -> dict:
         L = lib()

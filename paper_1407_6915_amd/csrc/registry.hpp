@@ -15,6 +15,9 @@ using sp_strided_launch_fn = void (*)(int dir, const void *in, void *out, const 
                                       const float *window, unsigned grid, hipStream_t s);
 using sp_rotated_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
                                       uint64_t batch, int rot, unsigned grid, hipStream_t s);
+using sp_indexed_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
+                                      const uint64_t *offs, uint64_t batch, unsigned grid,
+                                      hipStream_t s);
 using sp_real_launch_fn = void (*)(int dir, const void *in, void *out, const void *tw,
                                    const void *hw, uint64_t batch, unsigned grid,
                                    hipStream_t s);
@@ -54,6 +57,8 @@ struct SinglePassDesc {
     const void *kernel_strided[2];
     sp_real_launch_fn launch_real;  // real segments of length 2n (variant 0)
     const void *kernel_real[2];     // [0] forward (real in), [1] inverse (real out)
+    sp_indexed_launch_fn launch_indexed;  // segments at listed offsets
+    const void *kernel_indexed[2];
 };
 
 // Four-step pass A: N1-point column transforms, C columns per workgroup.
@@ -90,6 +95,10 @@ RowDesc split_row_desc(int config, int variant);
 // for outputs off a 128-byte line; null launcher if the length has none.
 // `variant` receives the table variant whose kernel it mirrors.
 sp_rotated_launch_fn rotated_launcher(uint64_t n, int *variant, const void **kernels);
+// One-pass kernels over segments at listed offsets (kernels_indexed.hip):
+// the work list's candidates for each of its one-pass lengths, `count`
+// receives how many there are (0 for other lengths); null if none.
+const SinglePassDesc *indexed_table(uint32_t n, int *count);
 // single-pass instances with one LDS pad element every 32 (kernels_pad.hip)
 SinglePassDesc pad32_desc(int config, int variant, int grid_mult);
 // four-step tiles with radix-32 stages (kernels_radix32.hip)

@@ -479,9 +479,13 @@ int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant
 int plan_build(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant,
                int forced_split_variants, uint64_t forced_n1)
 {
-    // 4 GiB of complex64 per scratch buffer (the radix-stage path has two)
+    // 4 GiB of complex64 per scratch buffer (the radix-stage path has two);
+    // FFTSEG_SUB_SAMPLES caps a sub-batch at fewer samples
+    uint64_t max_sub = 1ull << 29;
+    if (const char *e = getenv("FFTSEG_SUB_SAMPLES"))
+        max_sub = std::max<uint64_t>(1, std::min<uint64_t>(max_sub, strtoull(e, nullptr, 10)));
     int st = plan_choose(p, n, batch, dir, forced_variant, forced_split_variants, forced_n1,
-                         1ull << 29);
+                         max_sub);
     if (st != FFT_OK || p->kind == Plan::COPY)
         return st;
     hipError_t e;

@@ -20,10 +20,11 @@ namespace sp {
 // real-input kernels (one row per length); kPrefetch = the plainly written
 // kernel with the next segment's loads issued ahead (implies the classic
 // policy); kSplit = the kernel with split (real, then imaginary) LDS
-// exchanges; kW4 / kW8 = 4 / 8 waves per SIMD.
+// exchanges; kW4 / kW8 = 4 / 8 waves per SIMD; kIndexed = the row also
+// provides the kernel over segments at listed offsets.
 constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
               kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256,
-              kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096;
+              kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096, kIndexed = 8192;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -97,6 +98,18 @@ struct SpInst {
             hipLaunchKernelGGL((real_inverse_kernel<Sh, Pol>), g, b, 0, s, (const c32 *)in,
                                (c32 *)out, (const c32 *)tw, (const c32 *)hw, batch);
     }
+    static void launch_indexed(int dir, const void *in, void *out, const void *tw,
+                               const uint64_t *offs, uint64_t batch, unsigned grid,
+                               hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((single_pass_indexed_kernel<Sh, Pol, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, offs, batch);
+        else
+            hipLaunchKernelGGL((single_pass_indexed_kernel<Sh, Pol, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)out, (const c32 *)tw, offs, batch);
+    }
     static SinglePassDesc desc(int variant, int grid_mult)
     {
         SinglePassDesc d{};
@@ -116,6 +129,11 @@ struct SpInst {
         d.launch = &launch;
         d.kernel[0] = (const void *)kernel<-1>();
         d.kernel[1] = (const void *)kernel<1>();
+        if constexpr ((F & kIndexed) != 0) {
+            d.launch_indexed = &launch_indexed;
+            d.kernel_indexed[0] = (const void *)&single_pass_indexed_kernel<Sh, Pol, -1>;
+            d.kernel_indexed[1] = (const void *)&single_pass_indexed_kernel<Sh, Pol, 1>;
+        }
         if constexpr ((F & kAux) != 0) {
             d.launch_strided = &launch_strided;
             d.kernel_strided[0] = (const void *)&single_pass_strided_kernel<Sh, Pol, -1>;

@@ -37,13 +37,22 @@ struct Pipeline {
     void *dev[kDevSlots] = {nullptr, nullptr, nullptr};
     std::vector<ChunkEvents> ev;  // one set per chunk in flight ring
     int ring = 0;
+    hipEvent_t ref = nullptr;     // time origin of the per-chunk timeline
+    std::vector<fft_chunk_times_t> *times = nullptr;
 
-    int init(Plan *p, int ring_len)
+    int init(Plan *p, int ring_len, std::vector<fft_chunk_times_t> *timeline)
     {
         plan = p;
         ring = ring_len;
+        times = timeline;
+        if (times)
+            times->clear();
         bytes = p->batch * p->n * sizeof(c32);
         hipError_t e;
+        if ((e = hipEventCreate(&ref)) != hipSuccess) {
+            ref = nullptr;
+            return hip_error(e, "hipEventCreate");
+        }
         for (hipStream_t *s : {&s_in, &s_comp, &s_out})
             if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess)
                 return hip_error(e, "hipStreamCreate");
@@ -71,6 +80,8 @@ struct Pipeline {
             for (hipEvent_t q : {c.h2d0, c.h2d1, c.c0, c.c1, c.d2h0, c.d2h1})
                 if (q)
                     (void)hipEventDestroy(q);
+        if (ref)
+            (void)hipEventDestroy(ref);
         for (void *d : dev)
             if (d)
                 (void)hipFree(d);
@@ -91,6 +102,8 @@ struct Pipeline {
             if ((e = hipStreamWaitEvent(s_in, P.d2h1, 0)) != hipSuccess)
                 return hip_error(e, "hipStreamWaitEvent");
         }
+        if (c == 0)
+            (void)hipEventRecord(ref, s_in);
         (void)hipEventRecord(E.h2d0, s_in);
         if ((e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s_in)) != hipSuccess)
             return hip_error(e, "host-to-device copy");
@@ -120,6 +133,14 @@ struct Pipeline {
         (void)hipEventElapsedTime(&a, E.h2d0, E.h2d1);
         (void)hipEventElapsedTime(&b, E.c0, E.c1);
         (void)hipEventElapsedTime(&d, E.d2h0, E.d2h1);
+        if (times) {
+            // every event of chunk c on the GPU clock, from the first copy
+            float t[6] = {0, 0, 0, 0, 0, 0};
+            const hipEvent_t q[6] = {E.h2d0, E.h2d1, E.c0, E.c1, E.d2h0, E.d2h1};
+            for (int i = 0; i < 6; ++i)
+                (void)hipEventElapsedTime(&t[i], ref, q[i]);
+            times->push_back({c, t[0], t[1], t[2], t[3], t[4], t[5]});
+        }
         if (st) {
             st->h2d_s += a * 1e-3;
             st->compute_s += b * 1e-3;
@@ -176,10 +197,19 @@ struct PinnedRing {
 
 }  // namespace
 
-// pinned ring kept with the plan between calls (freed with the plan)
+// pinned ring kept with the plan between calls (freed with the plan), and
+// the per-chunk timeline of the plan's last streamed call
 struct StreamState {
     PinnedRing ring;
+    std::vector<fft_chunk_times_t> timeline;
 };
+
+StreamState *stream_state(Plan *p)
+{
+    if (!p->stream_state)
+        p->stream_state = new StreamState();
+    return static_cast<StreamState *>(p->stream_state);
+}
 
 void stream_state_free(Plan *p)
 {
@@ -212,15 +242,13 @@ extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn f
         if (n_chunks == 0)
             return set_ok();
         const double t_start = now_s();
-        if (!p->stream_state)
-            p->stream_state = new StreamState();
-        StreamState *S = static_cast<StreamState *>(p->stream_state);
+        StreamState *S = stream_state(p);
         const uint64_t bytes = p->batch * p->n * sizeof(c32);
         int st = S->ring.reserve(n_slots, bytes);
         if (st != FFT_OK)
             return st;
         Pipeline pl;
-        if ((st = pl.init(p, std::max(n_slots, kDevSlots) + 1)) != FFT_OK)
+        if ((st = pl.init(p, std::max(n_slots, kDevSlots) + 1, &S->timeline)) != FFT_OK)
             return st;
         const uint64_t lag = (uint64_t)n_slots - 1;  // chunks in flight before a drain
         uint64_t drained = 0;
@@ -337,7 +365,7 @@ extern "C" int fft_exec_stream_pinned(fft_plan_t plan, uint64_t n_chunks,
             return set_ok();
         const double t_start = now_s();
         Pipeline pl;
-        int st = pl.init(p, n_slots + kDevSlots);
+        int st = pl.init(p, n_slots + kDevSlots, &stream_state(p)->timeline);
         if (st != FFT_OK)
             return st;
         const uint64_t lag = (uint64_t)n_slots - 1;
@@ -525,4 +553,20 @@ extern "C" int fft_host_free(void *ptr)
     if (e != hipSuccess)
         return hip_error(e, "hipHostFree");
     return set_ok();
+}
+
+extern "C" int fft_stream_last_timeline(fft_plan_t plan, fft_chunk_times_t *out, size_t max)
+{
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p)
+        return set_error(FFT_ERR_INVALID_ARG, "plan is NULL");
+    if (!out && max)
+        return set_error(FFT_ERR_INVALID_ARG, "out is NULL");
+    const StreamState *S = static_cast<const StreamState *>(p->stream_state);
+    const size_t have = S ? S->timeline.size() : 0;
+    const size_t n = std::min(have, max);
+    for (size_t i = 0; i < n; ++i)
+        out[i] = S->timeline[i];
+    set_ok();
+    return (int)std::min<size_t>(have, (size_t)INT32_MAX);
 }

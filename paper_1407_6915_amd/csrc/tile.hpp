@@ -703,6 +703,62 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     }
 }
 
+// Indexed segments: segment s of the launch reads in + offs[3s] and writes
+// out + offs[3s + 1] (sample offsets; offs holds records of three words, the
+// third unused here), so a batch of one length whose segments sit anywhere
+// runs through the same tile as the dense kernel of that length: the
+// plainly written tile (Pol::kClassic), split exchanges (Pol::kSplit) or the
+// policy-driven tile.
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    single_pass_indexed_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
+                               const uint64_t *__restrict__ offs, uint64_t batch)
+{
+    using S0 = Stage<Sh, 0, 1>;
+    const int tid_tw = threadIdx.x;
+    const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
+    if constexpr (Pol::kSplit) {
+        __shared__ float lds[Pol::kLdsElems];
+        for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+            const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+            const int t = Pol::template thr<0>(tid);
+            const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+            const bool valid = seg < batch && Pol::active(tid);
+            const uint64_t io = valid ? offs[3 * seg] : 0, oo = valid ? offs[3 * seg + 1] : 0;
+            typename Pol::Ctx ctx{out + oo, valid};
+            const c32 *x = in + io;
+            c32 v[Sh::kMaxE];
+            if (ctx.valid)
+                st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+            tile_run_split<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
+        }
+    } else if constexpr (Pol::kClassic) {
+        __shared__ c32 lds[Pol::kLdsElems];
+        const int slot = Pol::template col<0>(tid_tw);
+        const int t = Pol::template thr<0>(tid_tw);
+        for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+            const uint64_t seg = g * Pol::S + slot;
+            const bool valid = seg < batch;
+            const uint64_t io = valid ? offs[3 * seg] : 0, oo = valid ? offs[3 * seg + 1] : 0;
+            typename Pol::Ctx ctx{out + oo, valid};
+            const c32 *x = in + io;
+            c32 v[Sh::kMaxE];
+            if (ctx.valid)
+                st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
+            tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid_tw, ctx);
+        }
+    } else {
+        __shared__ c32 lds[Pol::kLdsElems];
+        for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+            const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
+            const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
+            const bool valid = seg < batch && Pol::active(tid);
+            const uint64_t io = valid ? offs[3 * seg] : 0, oo = valid ? offs[3 * seg + 1] : 0;
+            single_tile<Sh, Pol, D>(lds, tw, tid, tid_tw, in + io, out + oo, valid);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Real-input segments of even length N = 2M through one M-point complex
 // transform.

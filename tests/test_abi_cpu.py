@@ -62,6 +62,7 @@ def test_host_alloc_argument_checks():
     assert not L.fft_host_alloc(0)
     assert L.fft_last_status() == -1 and fs.last_error()
     assert L.fft_host_free(None) == 0
+    assert L.fft_stream_last_timeline(None, None, 0) == -1
 
 
 def test_factorize_matches_lengths():

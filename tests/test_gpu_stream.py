@@ -149,8 +149,20 @@ def test_stream_library_pinned_buffers():
         for c in range(pool):
             sig.fill_ptr(c * batch * n, batch * n, ins[c].ptr)
         with fs.Plan(n, batch) as plan:
+            assert plan.stream_timeline() == []
             st = plan.exec_stream_pinned(chunks, [b.ptr for b in ins], [b.ptr for b in outs], 3)
+            tl = plan.stream_timeline()
         assert st["chunks_done"] == chunks
+        # one entry per chunk, each chunk's steps in order on the GPU clock,
+        # copies in issued in chunk order
+        assert [t["chunk"] for t in tl] == list(range(chunks))
+        assert tl[0]["h2d_start_ms"] >= 0.0
+        for t in tl:
+            seq = [t["h2d_start_ms"], t["h2d_end_ms"], t["compute_start_ms"],
+                   t["compute_end_ms"], t["d2h_start_ms"], t["d2h_end_ms"]]
+            assert all(a <= b for a, b in zip(seq, seq[1:])), t
+        for a, b in zip(tl, tl[1:]):
+            assert a["h2d_end_ms"] <= b["h2d_start_ms"]
         for c in range(pool):
             x = ins[c].view().reshape(batch, n).copy()
             y = outs[c].view().reshape(batch, n).copy()
