@@ -214,10 +214,16 @@ def main():
                     help="also time a plain device copy of the same size")
     ap.add_argument("--workload", default="large",
                     choices=["large", "small", "uneven", "streamed", "serving", "long",
-                             "real", "frames"],
+                             "real", "frames", "file", "lengths"],
                     help="large = the 4096-point x 262144 batch (the reported metric); "
                          "the others print their own JSON line")
     ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")
+    ap.add_argument("--lengths", default="16384,6000,4096,1000",
+                    help="lengths: segment lengths to time, 8 GiB each")
+    ap.add_argument("--file-gib", type=int, default=16,
+                    help="file: size of the signal file (GiB; shrunk to the free space)")
+    ap.add_argument("--file-dir", default="", help="file: directory (default $TMPDIR or /tmp)")
+    ap.add_argument("--io-threads", type=int, default=8, help="file: parallel pread/pwrite")
     ap.add_argument("--overlap-md", default="",
                     help="streamed: write the per-chunk copy/transform timeline here")
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per rate")

@@ -11,6 +11,14 @@ under profiles/.
            reads for the plain device copy of a known size in the same run
            (bench.py --copy-reference copies samples*8 bytes each way)
 
+  traffic_table <fetch.csv> <write.csv> <out.json> <copy samples> <pattern=samples>...
+           [-- <fetch command> <write command>]
+           HBM bytes per sample of every kernel whose name contains a
+           pattern (samples per dispatch given per pattern), scaled by the
+           same counters on identity_copy_kernel of copy samples * 8 bytes
+  counters <counter_collection.csv> <out.md> <command...>
+           per-kernel means of every counter of one --pmc run and the
+           conflict and wait ratios
   overlap  <kernel_trace.csv> <memory_copy_trace.csv> <out.md> <chunks> <command...>
            per-chunk host-to-device copy, transform and device-to-host copy
            intervals of the streamed runs (bench.py --workload streamed), and
@@ -100,6 +108,80 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, samples: int,
     }
     json.dump(out, open(out_json, "w"), indent=1)
     print(json.dumps(out))
+
+
+def traffic_table(fetch_csv: str, write_csv: str, out_json: str, copy_samples: int,
+                  samples_rules, commands=()) -> None:
+    """HBM bytes per sample of every kernel in the two counter runs, scaled
+    by what FETCH_SIZE / WRITE_SIZE read for identity_copy_kernel, which
+    moves copy_samples * 8 bytes each way per dispatch.  samples_rules:
+    [(substring of the kernel name, samples per dispatch)], first match
+    wins."""
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    mean = lambda v: sum(v) / len(v)           # noqa: E731
+    copy = [k for k in fetch if "identity_copy_kernel" in k]
+    if len(copy) != 1:
+        raise SystemExit("expected one identity_copy_kernel, got %s" % copy)
+    known = copy_samples * 8.0
+    f_scale = mean(fetch[copy[0]]) * 1024.0 / known
+    w_scale = mean(write[copy[0]]) * 1024.0 / known
+    rows = []
+    for k in sorted(fetch):
+        if k not in write or k == copy[0]:
+            continue
+        samples = next((sp for pat, sp in samples_rules if pat in k), None)
+        if samples is None:
+            continue
+        fb = mean(fetch[k]) * 1024.0 / f_scale
+        wb = mean(write[k]) * 1024.0 / w_scale
+        rows.append({"kernel": _short(k), "dispatches": len(fetch[k]),
+                     "samples_per_dispatch": samples,
+                     "fetch_KiB_per_dispatch": mean(fetch[k]),
+                     "write_KiB_per_dispatch": mean(write[k]),
+                     "hbm_read_bytes_per_sample": fb / samples,
+                     "hbm_write_bytes_per_sample": wb / samples,
+                     "hbm_bytes_per_sample": (fb + wb) / samples,
+                     "algorithmic_bytes_per_sample": 16.0})
+    out = {"copy_kernel": _short(copy[0]), "copy_bytes_each_way": known,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": rows,
+           "commands": list(commands)}
+    json.dump(out, open(out_json, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def counters(counter_csv: str, out_md: str, command: str) -> None:
+    """Per-kernel means of every counter in one --pmc run, plus the derived
+    ratios used to read them: LDS bank-conflict cycles per LDS instruction,
+    and the share of wave cycles spent waiting (SQ_WAIT_ANY) and waiting
+    to issue (SQ_WAIT_INST_ANY)."""
+    per = {}
+    for r in csv.DictReader(open(counter_csv)):
+        d = per.setdefault(r["Kernel_Name"], {"vgpr": r.get("VGPR_Count", ""),
+                                             "lds": r.get("LDS_Block_Size", ""),
+                                             "wg": r.get("Workgroup_Size", "")})
+        d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for d in per.values() for c in d if c not in ("vgpr", "lds", "wg")})
+    lines = ["# Counters per kernel", "", "Command (run from the repository root):", "",
+             "    " + command, "",
+             "Means over each kernel's dispatches.  conflict/LDS = SQ_LDS_BANK_CONFLICT / "
+             "SQ_INSTS_LDS; wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES; issue wait = "
+             "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.", "",
+             "| kernel | workgroup | VGPRs | LDS bytes | " + " | ".join(names) +
+             " | conflict/LDS | wait | issue wait |",
+             "|---|---|---|---|" + "---|" * len(names) + "---|---|---|"]
+    for k, d in per.items():
+        if k.startswith("__amd") or "at::native" in k:
+            continue
+        m = {c: sum(d[c]) / len(d[c]) for c in names if c in d}
+        ratio = lambda a, b: ("%.2f" % (m[a] / m[b])) if m.get(b) else "—"  # noqa: E731
+        lines.append("| `%s` | %s | %s | %s | " % (_short(k)[:150], d["wg"], d["vgpr"], d["lds"]) +
+                     " | ".join("%.3g" % m[c] if c in m else "—" for c in names) + " | " +
+                     " | ".join([ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS"),
+                                 ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES"),
+                                 ratio("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")]) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _col(row, *names):
@@ -247,6 +329,15 @@ if __name__ == "__main__":
         kernels(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6:8])
+    elif sys.argv[1] == "traffic_table":
+        # fetch.csv write.csv out.json copy_samples pattern=samples ... -- commands
+        args = sys.argv[2:]
+        cmds = args[args.index("--") + 1:] if "--" in args else []
+        args = args[:args.index("--")] if "--" in args else args
+        rules = [(a.split("=", 1)[0], int(a.split("=", 1)[1])) for a in args[4:]]
+        traffic_table(args[0], args[1], args[2], int(args[3]), rules, cmds)
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "overlap":
         overlap(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), " ".join(sys.argv[6:]))
     else:

@@ -70,6 +70,7 @@ def uneven(args):
     ent["in_off"] = ent["out_off"] = in_off
     ent["segment_len"] = lengths
     sh = torch.cuda.current_stream().cuda_stream
+    fs.tune_clear()
     t_build = time.perf_counter()
     wl = fs.WorkList(ent)
     t_build = time.perf_counter() - t_build
@@ -79,6 +80,25 @@ def uneven(args):
     wl.status()
     desc = wl.describe()
     wl.close()
+    # tuned: each one-pass length's plan variant, grid and work-list route
+    # picked by fft_autotune on as many segments as the list holds of it
+    t0 = time.perf_counter()
+    tuned = {}
+    for n in workloads.UNEVEN_LENGTHS:
+        if fs.indexed_count(n) == 0:
+            continue
+        c = int((lengths == n).sum())
+        best = fs.autotune(n, c)
+        tuned[str(n)] = best
+    t_tune = time.perf_counter() - t0
+    wl = fs.WorkList(ent)
+    t_wl_t = _time(torch, lambda: wl.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
+    t_graph_t = _time(torch, lambda: wl.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh, graph=True),
+                      args.steps)
+    wl.status()
+    desc_t = wl.describe()
+    wl.close()
+    fs.tune_clear()
     # reference: one plain batched launch per length over length-sorted data
     per_len = {}
     bufs = {}
@@ -102,6 +122,10 @@ def uneven(args):
     out = {"workload": workloads.UNEVEN["name"], "segments": len(lengths), "samples": total,
            "worklist": desc, "build_s": round(t_build, 3),
            "persistent_ms": round(t_wl * 1e3, 3), "persistent_graph_ms": round(t_graph * 1e3, 3),
+           "tuned": {"persistent_ms": round(t_wl_t * 1e3, 3),
+                     "persistent_graph_ms": round(t_graph_t * 1e3, 3),
+                     "indexed": desc_t.get("indexed"), "tune_s": round(t_tune, 1),
+                     "best_us_per_length": tuned},
            "per_length_plain_ms": round(t_plain * 1e3, 3), "per_length_ms": per_len,
            "GFLOP/s": {"persistent": round(flops / t_wl / 1e9, 1),
                        "persistent_graph": round(flops / t_graph / 1e9, 1),
@@ -292,8 +316,9 @@ def serving(args):
     fifo_arena = torch.empty(cap, dtype=torch.complex64, device="cuda")
     budget_bytes = 200 * 10 ** 9
     max_launch = 1 << 31                                   # bounds the two-pass scratch
-    arena_samples = (budget_bytes - max_launch * 8) // 8
-    ex = GpuExecutor(arena_samples, max_launch_samples=max_launch)
+    # the arena gets what the work list's reserved device memory leaves
+    ex = GpuExecutor(max_launch_samples=max_launch, hbm_budget_bytes=budget_bytes)
+    arena_samples = ex.arena_samples
     # saturation: the same jobs, every one queued at t = 0, through each path
     sat_f = job_states(1e9, min(args.jobs, 300), 99)
     sat_c = [JobState(j.index, j.arrival_s, j.seg_len, j.n_seg, j.host_in, j.host_out)
@@ -331,7 +356,10 @@ def serving(args):
                       "saturation_payload_GBps": {
                           "plain": round(st_sat["samples_per_s"] * 8 / 1e9, 2),
                           "continuous": round(st_sat_c["samples_per_s"] * 8 / 1e9, 2)},
-                      "hbm_budget_bytes": budget_bytes, "pool_fill_s": round(t_pool, 2),
+                      "hbm_budget_bytes": budget_bytes,
+                      "device_footprint_bytes": arena_samples * 8 + ex.resident_bytes,
+                      "worklist_resident_bytes": ex.resident_bytes,
+                      "pool_fill_s": round(t_pool, 2),
                       "rates": rows}), flush=True)
     return 0
 
@@ -464,7 +492,142 @@ def frames(args):
     return 0
 
 
+def lengths(args):
+    """Plain batched plans of the listed lengths, each over 8 GiB resident in
+    HBM (the kernel-level rates behind the one-pass and two-pass rows; a
+    driver for counter runs)."""
+    import torch
+    import paper_1407_6915_amd as fs
+    total = 1 << 30
+    g = torch.Generator(device="cuda").manual_seed(0x14076917)
+    x = torch.randn(total, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    sh = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for n in [int(v) for v in args.lengths.split(",") if v]:
+        b = total // n
+        with fs.Plan(n, b) as p:
+            t = _time(torch, lambda: p.exec_ptr(x.data_ptr(), y.data_ptr(), sh), args.steps)
+            d = p.describe()
+        passes = 2 if d.get("kind") == "four_step" else 1
+        rows.append({"segment_len": n, "batch": b, "kind": d.get("kind"),
+                     "variant": d.get("variant"), "ms": round(t * 1e3, 3),
+                     "GFLOP/s": round(FLOP(n) * b / t / 1e9, 1),
+                     "algorithmic_GBps": round(16.0 * b * n / t / 1e9, 1),
+                     "plan_traffic_GBps": round(16.0 * passes * b * n / t / 1e9, 1)})
+    print(json.dumps({"workload": "lengths_in_hbm", "rows": rows}), flush=True)
+    return 0
+
+
+def _fs_type(path):
+    """Filesystem type of the mount holding path (from /proc/mounts)."""
+    import os
+    path = os.path.realpath(path)
+    best, kind = "", "unknown"
+    try:
+        for line in open("/proc/mounts"):
+            parts = line.split()
+            if len(parts) >= 3 and path.startswith(parts[1]) and len(parts[1]) > len(best):
+                best, kind = parts[1], parts[2]
+    except OSError:
+        pass
+    return kind
+
+
+def file(args):
+    """File in, file out (the paper's setting, Sec. III-IV): a signal file of
+    4096-point segments on the box's local disk, read in 1 GiB chunks into
+    the pinned ring, transformed, and each chunk's spectra written at the
+    same offset of an output file.  The input is written first, flushed and
+    dropped from the page cache, so the reads come from the device under the
+    file system.  Reports read and write GB/s, host-link GB/s, transform
+    time and the time shares, next to the paper's (FFT 5-8 % of the GPU
+    run, I/O the rest)."""
+    import os
+    import shutil
+    import paper_1407_6915_amd as fs
+    from siggen import segment_energy, workloads
+    n = workloads.LARGE["seg_len"]
+    seg = 1 << 17                       # 1 GiB chunks
+    chunk = n * seg * 8
+    d = args.file_dir or os.environ.get("TMPDIR", "/tmp")
+    free = shutil.disk_usage(d).free
+    want = args.file_gib << 30
+    size = min(want, max(0, (free - (8 << 30)) // 2) // chunk * chunk)
+    if size < 2 * chunk:
+        print(json.dumps({"workload": "file", "skipped": "only %.1f GiB free in %s"
+                          % (free / 2 ** 30, d)}), flush=True)
+        return 0
+    chunks = size // chunk
+    fin = os.path.join(d, "fftseg_bench_in_%d.bin" % os.getpid())
+    fout = os.path.join(d, "fftseg_bench_out_%d.bin" % os.getpid())
+    sig = workloads.large_signal()
+    buf = fs.HostBuffer(chunk)
+    try:
+        t0 = time.perf_counter()
+        fd = os.open(fin, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o644)
+        try:
+            v = buf.view()
+            for c in range(chunks):
+                sig.fill_ptr(c * n * seg, n * seg, buf.ptr)
+                mv = memoryview(v.view(np.uint8))
+                off = 0
+                while off < chunk:
+                    off += os.pwrite(fd, mv[off:], c * chunk + off)
+            os.fsync(fd)
+            os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+        finally:
+            os.close(fd)
+        t_write_in = time.perf_counter() - t0
+        with fs.Plan(n, seg) as plan:
+            rc, failed, st = plan.exec_file(fin, fout, chunks, n_slots=3,
+                                            io_threads=args.io_threads)
+            tl = plan.stream_timeline()
+        if rc != 0:
+            raise RuntimeError("file run failed at chunk %s (status %d)" % (failed, rc))
+        # Parseval on every segment of the first and last chunk
+        dev = 0.0
+        with open(fout, "rb") as f:
+            for c in sorted({0, chunks - 1}):
+                f.seek(c * chunk)
+                y = np.frombuffer(f.read(chunk), np.complex64).reshape(seg, n)
+                _, e_in = sig.segments_with_energy(c * seg, seg)
+                dev = max(dev, float(np.max(np.abs(segment_energy(y) / (n * e_in) - 1.0))))
+        import bench_profile
+        H, K, D = bench_profile.timeline_intervals(tl)
+        ov = bench_profile.overlap_stats(H, [iv for ks in K for iv in ks], D)
+        wall = st["wall_s"]
+        out = {"workload": "file_%s_4096pt" % ("%dGiB" % (size >> 30)),
+               "file_bytes": size, "chunks": chunks, "chunk_bytes": chunk,
+               "dir": d, "filesystem": _fs_type(d), "io_threads": args.io_threads,
+               "input_write_s": round(t_write_in, 2),
+               "wall_s": round(wall, 3),
+               "end_to_end_GBps": round(size / wall / 1e9, 2),
+               "file_read_GBps": round(size / max(st["fill_s"], 1e-9) / 1e9, 2),
+               "file_write_GBps": round(size / max(st["drain_s"], 1e-9) / 1e9, 2),
+               "read_s": round(st["fill_s"], 3), "write_s": round(st["drain_s"], 3),
+               "h2d_GBps_per_copy": round(size / max(st["h2d_s"], 1e-9) / 1e9, 2),
+               "d2h_GBps_per_copy": round(size / max(st["d2h_s"], 1e-9) / 1e9, 2),
+               "transform_s": round(st["compute_s"], 4),
+               "share_transform": round(st["compute_s"] / wall, 4),
+               "share_file_io": round((st["fill_s"] + st["drain_s"]) / wall, 4),
+               "device_idle_ms": round(ov["device_idle_ms"], 1),
+               "paper_context": "GPU run: FFT 5-8 % of the time, I/O the rest; CPU run: "
+                                "disk I/O 70-75 % (Sec. IV, Figs. 4-5)",
+               "parseval_max_rel_dev_first_last_chunk": dev,
+               "parseval_bound": 2 * 5e-7 * math.log2(n) + (5e-7 * math.log2(n)) ** 2}
+        print(json.dumps(out), flush=True)
+        return 0 if dev <= out["parseval_bound"] else 1
+    finally:
+        buf.close()
+        for p in (fin, fout):
+            try:
+                os.remove(p)
+            except OSError:
+                pass
+
+
 def run(args):
     return {"small": small, "uneven": uneven, "streamed": streamed,
             "serving": serving, "long": long, "real": real,
-            "frames": frames}[args.workload](args)
+            "frames": frames, "file": file, "lengths": lengths}[args.workload](args)

@@ -301,6 +301,15 @@ typedef struct fftseg_worklist *fft_worklist_t;
  * four-step plan the work list keeps), else 0. */
 int fft_worklist_supported(uint32_t segment_len);
 
+/* Number of indexed kernels a work list can send segments of this length
+ * through: launches of their own over the segments' listed offsets,
+ * instead of the work-list kernel's tiles.  One-pass lengths: the indexed
+ * one-pass kernels; 65536: 1, its two passes as launches of their own; 0
+ * for 16384, 2^20 and unsupported lengths.  Route 0 is the tiles, route
+ * 1 + k the k-th indexed kernel; fft_autotune picks one per length,
+ * untuned lengths take route 1. */
+int fft_worklist_indexed_count(uint32_t segment_len);
+
 /* Compile n entries into workgroup tasks: segments are grouped by length,
  * packed S per tile for short lengths, split into column/row tiles for the
  * two-pass lengths; 16384-point segments become "wide" tiles of their own
@@ -402,7 +411,12 @@ int fft_exec_segments_graph(fft_plan_t plan, const void *in, void *out, void *st
  * other split n1' x n/n1' with compiled tiles, at each grid size), on
  * device buffers of batch segments it allocates and frees.  The fastest
  * choice goes into the process-wide tuning table used by later plans and,
- * if path != NULL, is merged into that JSON cache file.  Returns the number
+ * if path != NULL, is merged into that JSON cache file.  For a one-pass
+ * length that work lists support it also picks the work-list route (Sec.
+ * III's batching of a block into one launch): the work-list kernel's tiles,
+ * or a launch of its own through each indexed one-pass kernel of the length
+ * at each grid size, timed on `batch` segments packed at odd offsets; work
+ * lists built later use the winner.  Returns the number
  * of configurations timed (negative status on error); *best_us (may be
  * NULL) receives the winner's time per exec in microseconds. */
 int fft_autotune(size_t segment_len, size_t batch, int direction, const char *path,

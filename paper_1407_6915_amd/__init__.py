@@ -138,6 +138,7 @@ def lib():
                                    i32, i32, ctypes.POINTER(u64), ctypes.POINTER(StreamStats)])
     _sig(L, "fft_exec_frames", i32, [vp, vp, sz, vp, sz, sz, vp, vp])
     _sig(L, "fft_worklist_supported", i32, [ctypes.c_uint32])
+    _sig(L, "fft_worklist_indexed_count", i32, [ctypes.c_uint32])
     _sig(L, "fft_worklist_create", vp, [ctypes.POINTER(WorkItem), sz, i32])
     _sig(L, "fft_worklist_reset", i32, [vp, ctypes.POINTER(WorkItem), sz, vp])
     _sig(L, "fft_worklist_exec", i32, [vp, vp, vp, vp])
@@ -585,6 +586,11 @@ def worklist_cache_clear() -> None:
 
 def worklist_supported(n: int) -> bool:
     return bool(lib().fft_worklist_supported(n))
+
+
+def indexed_count(n: int) -> int:
+    """Indexed one-pass kernels a work list can route length n through."""
+    return int(lib().fft_worklist_indexed_count(n))
 
 
 def autotune(segment_len: int, batch: int, direction: int = FORWARD,

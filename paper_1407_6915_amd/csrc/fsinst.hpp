@@ -15,9 +15,11 @@ namespace fs {
 // 4 / 8 waves per SIMD; the column pass also comes in a form that reads
 // overlapping, windowed frames; both passes also come in a form whose blocks
 // start at any column / row and wrap round (for segments off a line
-// boundary); one row per length carries each of these forms
+// boundary); both passes also come in a form over segments at listed
+// offsets (kIndexed); one row per length carries each of these forms
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
-              kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048;
+              kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048,
+              kIndexed = 4096;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -87,6 +89,21 @@ struct ColInst {
                                (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
                                (const c32 *)th, sh, n2, batch, hop, window);
     }
+    static void launch_indexed(int dir, const void *in, void *ybuf, const void *tw,
+                               const void *tl, const void *th, int sh, int n2,
+                               const uint64_t *offs, uint64_t batch, unsigned grid,
+                               hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_columns_indexed_kernel<Sh, PolW, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, offs, batch);
+        else
+            hipLaunchKernelGGL((four_step_columns_indexed_kernel<Sh, PolW, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, offs, batch);
+    }
     static ColumnDesc desc(int variant)
     {
         ColumnDesc d{};
@@ -112,6 +129,11 @@ struct ColInst {
             d.launch_shifted = &launch_shifted;
             d.kernel_shifted[0] = (const void *)&four_step_columns_shifted_kernel<Sh, PolW, -1>;
             d.kernel_shifted[1] = (const void *)&four_step_columns_shifted_kernel<Sh, PolW, 1>;
+        }
+        if constexpr ((F & kIndexed) != 0) {
+            d.launch_indexed = &launch_indexed;
+            d.kernel_indexed[0] = (const void *)&four_step_columns_indexed_kernel<Sh, PolW, -1>;
+            d.kernel_indexed[1] = (const void *)&four_step_columns_indexed_kernel<Sh, PolW, 1>;
         }
         return d;
     }
@@ -148,6 +170,20 @@ struct RowInst {
             hipLaunchKernelGGL((four_step_rows_kernel<Sh, Pol, 1>), g, b, 0, s,
                                (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch);
     }
+    static void launch_indexed(int dir, const void *in, const void *ybuf, void *out,
+                               const void *tw, int n1, const uint64_t *offs, uint64_t batch,
+                               unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_rows_indexed_kernel<Sh, PolW, -1>), g, b, 0, s,
+                               (const c32 *)in, (const c32 *)ybuf, (c32 *)out,
+                               (const c32 *)tw, n1, offs, batch);
+        else
+            hipLaunchKernelGGL((four_step_rows_indexed_kernel<Sh, PolW, 1>), g, b, 0, s,
+                               (const c32 *)in, (const c32 *)ybuf, (c32 *)out,
+                               (const c32 *)tw, n1, offs, batch);
+    }
     static RowDesc desc(int variant)
     {
         RowDesc d{};
@@ -168,6 +204,11 @@ struct RowInst {
             d.launch_shifted = &launch_shifted;
             d.kernel_shifted[0] = (const void *)&four_step_rows_shifted_kernel<Sh, PolW, -1>;
             d.kernel_shifted[1] = (const void *)&four_step_rows_shifted_kernel<Sh, PolW, 1>;
+        }
+        if constexpr ((F & kIndexed) != 0) {
+            d.launch_indexed = &launch_indexed;
+            d.kernel_indexed[0] = (const void *)&four_step_rows_indexed_kernel<Sh, PolW, -1>;
+            d.kernel_indexed[1] = (const void *)&four_step_rows_indexed_kernel<Sh, PolW, 1>;
         }
         return d;
     }

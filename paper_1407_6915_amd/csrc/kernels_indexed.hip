@@ -4,6 +4,7 @@
 // segments, wherever they sit in the list, run at that length's plain rate.
 // Kept in a translation unit of their own so they do not share inlined code
 // with the dense instances.
+#include "fsinst.hpp"
 #include "spinst.hpp"
 
 namespace fftseg {
@@ -42,7 +43,24 @@ const SinglePassDesc kIdx16384[] = {
     SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kIndexed, 16, 32, 32>::desc(0, 32),
 };
 
+// the 65536-point two-pass tiles (256 x 256), as the plan's defaults
+const ColumnDesc kIdxCol65536 =
+    fs::ColInst<256, 16, 16, 4, fs::kNT | fs::kXcd | fs::kHoistLast | fs::kIndexed, 16,
+                16>::desc(0);
+const RowDesc kIdxRow65536 =
+    fs::RowInst<256, 16, 16, 4, fs::kNT | fs::kXcd | fs::kHoistLast | fs::kIndexed, 16,
+                16>::desc(0);
+
 }  // namespace
+
+bool indexed_four_step(uint32_t n, const ColumnDesc **col, const RowDesc **row)
+{
+    if (n != 65536)
+        return false;
+    *col = &kIdxCol65536;
+    *row = &kIdxRow65536;
+    return true;
+}
 
 const SinglePassDesc *indexed_table(uint32_t n, int *count)
 {

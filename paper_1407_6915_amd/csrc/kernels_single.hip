@@ -71,6 +71,7 @@ const SinglePassDesc kTable[] = {
     split_desc(1, 4, 32),
     split_desc(2, 5, 32),
     split_desc(3, 6, 32),
+    split_desc(4, 7, 32),
     // mixed radix 2/3/5
     SpInst<1000, 100, 2, 4, kClassic, 10, 10, 10>::desc(0, 64),
     SpInst<1000, 100, 2, 4, kPlain, 10, 10, 10>::desc(1, 64),
@@ -85,6 +86,13 @@ const SinglePassDesc kTable[] = {
     SpInst<6000, 300, 1, 4, kNT | kNoHoist | kAux, 20, 20, 15>::desc(2, 32),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist | kPlain, 16, 15, 25>::desc(3, 32),
     SpInst<6000, 400, 1, 4, kPrefetch | kNT, 16, 15, 25>::desc(4, 32),
+    // cached loads and stores (stage 0 reads 375-sample runs that straddle
+    // lines; streamed loads fetch the shared lines twice)
+    SpInst<6000, 400, 1, 4, kClassic, 16, 15, 25>::desc(5, 32),
+    // radix 15 or 25 first: stage 0 reads at strides of 400 or 240 samples,
+    // whole lines
+    SpInst<6000, 400, 1, 4, kClassic | kNT, 15, 25, 16>::desc(6, 32),
+    SpInst<6000, 400, 1, 4, kClassic | kNT, 25, 15, 16>::desc(7, 32),
 };
 
 }  // namespace

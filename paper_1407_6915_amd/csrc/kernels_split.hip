@@ -25,6 +25,11 @@ SinglePassDesc split_desc(int config, int variant, int grid_mult)
     case 3:
         return SpInst<16384, 512, 1, 4, kSplit | kPrefetch | kNT | kNoHoist | kW2, 32, 32,
                       16>::desc(variant, grid_mult);
+    case 4:
+        // 1024 threads, 16 values each: two workgroups per CU give 32 waves
+        // (8 per SIMD, 64 VGPRs) instead of 16
+        return SpInst<16384, 1024, 1, 4, kSplit | kNT | kNoHoist | kW8, 16, 16, 16, 4>::desc(
+            variant, grid_mult);
     default:
         return SinglePassDesc{};
     }

@@ -32,6 +32,13 @@ using col_shifted_launch_fn = void (*)(int dir, const void *in, void *ybuf, cons
 using row_shifted_launch_fn = void (*)(int dir, const void *ybuf, void *out, const void *tw,
                                        int n1, uint64_t batch, int shift, unsigned grid,
                                        hipStream_t s);
+using col_indexed_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
+                                       const void *tl, const void *th, int sh, int n2,
+                                       const uint64_t *offs, uint64_t batch, unsigned grid,
+                                       hipStream_t s);
+using row_indexed_launch_fn = void (*)(int dir, const void *in, const void *ybuf, void *out,
+                                       const void *tw, int n1, const uint64_t *offs,
+                                       uint64_t batch, unsigned grid, hipStream_t s);
 using col_frames_launch_fn = void (*)(int dir, const void *in, void *ybuf, const void *tw,
                                       const void *tl, const void *th, int sh, int n2,
                                       uint64_t batch, uint64_t hop, const float *window,
@@ -71,6 +78,8 @@ struct ColumnDesc {
     const void *kernel_frames[2];
     col_shifted_launch_fn launch_shifted;  // blocks from a column offset, wrapping
     const void *kernel_shifted[2];
+    col_indexed_launch_fn launch_indexed;  // segments at listed offsets
+    const void *kernel_indexed[2];
 };
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.
@@ -81,6 +90,8 @@ struct RowDesc {
     const void *kernel[2];
     row_shifted_launch_fn launch_shifted;  // blocks from a row offset, wrapping
     const void *kernel_shifted[2];
+    row_indexed_launch_fn launch_indexed;  // segments at listed offsets
+    const void *kernel_indexed[2];
 };
 
 const SinglePassDesc *single_pass_table(int *count);
@@ -99,6 +110,10 @@ sp_rotated_launch_fn rotated_launcher(uint64_t n, int *variant, const void **ker
 // the work list's candidates for each of its one-pass lengths, `count`
 // receives how many there are (0 for other lengths); null if none.
 const SinglePassDesc *indexed_table(uint32_t n, int *count);
+// The two passes over segments at listed offsets for the work list's
+// two-pass length n (kernels_indexed.hip); false if n has none.  Each
+// segment's Y takes n + 16 samples of scratch.
+bool indexed_four_step(uint32_t n, const ColumnDesc **col, const RowDesc **row);
 // single-pass instances with one LDS pad element every 32 (kernels_pad.hip)
 SinglePassDesc pad32_desc(int config, int variant, int grid_mult);
 // four-step tiles with radix-32 stages (kernels_radix32.hip)

@@ -169,6 +169,18 @@ void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant, uint64
         }
 }
 
+int tuned_wl_route(uint64_t n, int *grid)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.n == n) {
+            if (grid)
+                *grid = p.wl_grid;
+            return p.wl_route;
+        }
+    return -1;
+}
+
 void set_tuned(const TunedChoice &c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -177,6 +189,23 @@ void set_tuned(const TunedChoice &c)
             p = c;
             return;
         }
+    g_tuned.push_back(c);
+}
+
+void set_tuned_wl_route(uint64_t n, int route, int grid, double us)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &p : g_tuned)
+        if (p.n == n) {
+            p.wl_route = route;
+            p.wl_grid = grid;
+            p.wl_us = us;
+            return;
+        }
+    TunedChoice c{n, -2, 0, 0, 0, 0, 0};  // variant -2: no plan choice
+    c.wl_route = route;
+    c.wl_grid = grid;
+    c.wl_us = us;
     g_tuned.push_back(c);
 }
 

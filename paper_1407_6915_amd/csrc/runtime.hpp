@@ -110,8 +110,21 @@ struct TunedChoice {
     int col_variant;  // two-pass plans: column and row tile variants
     int row_variant;
     uint64_t n1 = 0;  // two-pass plans: column length of the split (0: the planner's)
+    // work lists, one-pass lengths: -1 not tuned, 0 the work-list kernel's
+    // tiles, 1 + k the k-th indexed one-pass kernel of the length, at
+    // wl_grid resident workgroup waves per CU
+    int wl_route = -1;
+    int wl_grid = 0;
+    double wl_us = 0;  // its measured time per exec
 };
+// persistent grid of the four-step passes by column length: resident
+// workgroup waves per CU
+int two_pass_grid_mult(uint64_t n1);
 int tuned_variant(uint64_t n);
+// the tuned work-list route of length n (-1 if none) and its grid
+int tuned_wl_route(uint64_t n, int *grid);
+// record a work-list route for n without touching the plan choice
+void set_tuned_wl_route(uint64_t n, int route, int grid, double us);
 int tuned_grid_mult(uint64_t n, int variant, int fallback);
 void tuned_split_variants(uint64_t n, int *col_variant, int *row_variant, uint64_t *n1);
 void set_tuned(const TunedChoice &c);

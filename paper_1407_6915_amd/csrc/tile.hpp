@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 }
 
 template <class Sh, class Pol, int D>
-__global__ void __launch_bounds__(Pol::kThreads)
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
     single_pass_plain_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
                              uint64_t batch)
 {
@@ -1221,6 +1221,71 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         const int first = (int)(g - seg * blocks) * Pol::C + shift;
         row_tile<Sh, Pol, D>(lds, tw, Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(),
                              threadIdx.x, ybuf + seg * nseg, out + seg * nseg, first, n1);
+    }
+}
+
+// Both passes over segments at listed offsets (offs holds records of three
+// words per segment: input offset, output offset, unused; sample units).
+// Segment s keeps its Y at ybuf + s * (N + 16), plus the input's offset
+// within a 128-byte line (16 samples), and each pass starts its blocks at
+// the first column (row) whose address in x (out) is line-aligned, wrapping
+// round, as the shifted kernels do for a whole batch: every block then
+// reads and writes whole lines wherever the caller's segments start.
+constexpr int kIdxLine = 16;
+
+__device__ __forceinline__ int line_offset(const c32 *p)
+{
+    return (int)(((uintptr_t)p / sizeof(c32)) & (kIdxLine - 1));
+}
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    four_step_columns_indexed_kernel(const c32 *in, c32 *ybuf, const c32 *__restrict__ tw,
+                                     const c32 *__restrict__ tl, const c32 *__restrict__ th,
+                                     int sh, int n2, const uint64_t *__restrict__ offs,
+                                     uint64_t batch)
+{
+    static_assert(Pol::kWrap, "blocks wrap round");
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
+    const uint64_t blocks = (uint64_t)(n2 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
+        const uint64_t seg = g / blocks;
+        const c32 *x = in + offs[3 * seg];
+        const int in_m = line_offset(x);
+        const int first = (int)(g - seg * blocks) * Pol::C + ((kIdxLine - in_m) & (kIdxLine - 1));
+        column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
+                                Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
+                                x, ybuf + seg * (nseg + kIdxLine) + in_m, first, n2);
+    }
+}
+
+template <class Sh, class Pol, int D>
+__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+    four_step_rows_indexed_kernel(const c32 *in, const c32 *ybuf, c32 *out,
+                                  const c32 *__restrict__ tw, int n1,
+                                  const uint64_t *__restrict__ offs, uint64_t batch)
+{
+    static_assert(Pol::kWrap, "blocks wrap round");
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
+    const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n1;
+    const uint64_t blocks = (uint64_t)(n1 / Pol::C);
+    const uint64_t tiles = batch * blocks;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+        const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
+        if (g >= tiles)
+            continue;
+        const uint64_t seg = g / blocks;
+        const int in_m = line_offset(in + offs[3 * seg]);
+        c32 *y = out + offs[3 * seg + 1];
+        const int first =
+            (int)(g - seg * blocks) * Pol::C + ((kIdxLine - line_offset(y)) & (kIdxLine - 1));
+        row_tile<Sh, Pol, D>(lds, tw, Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(),
+                             threadIdx.x, ybuf + seg * (nseg + kIdxLine) + in_m, y, first, n1);
     }
 }
 

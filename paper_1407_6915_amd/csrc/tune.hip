@@ -62,6 +62,81 @@ int time_plan(Plan *p, void *in, void *out, hipStream_t s, int reps, double *us)
     return FFT_OK;
 }
 
+// Work-list route of a length with indexed kernels: batch segments at sample offsets
+// s * (n + 3), so they start at every position within a cache line as in
+// a packed mixed list, through the work-list kernel's tiles (route 0) and
+// through each indexed one-pass kernel of the length (route 1 + k) at each
+// grid size; the fastest goes into *route, *grid, *us.  Returns the number
+// of configurations timed (0 if the length has no work-list tiles or no
+// indexed kernel), or a negative status.
+int tune_worklist_route(uint64_t n, uint64_t batch, int dir, hipStream_t s, int *route,
+                        int *grid, double *us_best)
+{
+    const int cnt = fft_worklist_indexed_count((uint32_t)n);
+    if (cnt == 0)
+        return 0;
+    const uint64_t stride = n + 3, total = batch * stride;
+    void *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, total * sizeof(c32)) != hipSuccess ||
+        hipMalloc(&out, total * sizeof(c32)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (in)
+            (void)hipFree(in);
+        return set_error(FFT_ERR_OUT_OF_MEMORY, "work-list tuning buffers");
+    }
+    (void)hipMemset(in, 0, total * sizeof(c32));
+    std::vector<fft_work_t> items(batch);
+    for (uint64_t i = 0; i < batch; ++i)
+        items[i] = {i * stride, i * stride, (uint32_t)n, 0};
+    // the route in the table while tuning is restored afterwards
+    int keep_grid = 0;
+    const int keep_route = tuned_wl_route(n, &keep_grid);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int timed = 0, st = FFT_OK;
+    double best = 1e300;
+    for (int r = 0; r <= cnt && st == FFT_OK; ++r) {
+        for (int m : kMults) {
+            if (r == 0 && m != kMults[0])
+                break;  // the tiles' grid is the work list's own
+            set_tuned_wl_route(n, r, m, 0);
+            fft_worklist_t w = fft_worklist_create(items.data(), batch, dir);
+            if (!w) {
+                st = last_status();
+                break;
+            }
+            for (int i = 0; i < 2 && st == FFT_OK; ++i)
+                st = fft_worklist_exec(w, in, out, s);
+            (void)hipEventRecord(e0, s);
+            for (int i = 0; i < 5 && st == FFT_OK; ++i)
+                st = fft_worklist_exec(w, in, out, s);
+            (void)hipEventRecord(e1, s);
+            float ms = 0;
+            if (st == FFT_OK && hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                const double us = ms * 1e3 / 5;
+                ++timed;
+                if (us < best) {
+                    best = us;
+                    *route = r;
+                    *grid = r == 0 ? 0 : m;
+                }
+            }
+            fft_worklist_destroy(w);
+        }
+    }
+    set_tuned_wl_route(n, keep_route, keep_grid, 0);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    if (st != FFT_OK)
+        return st;
+    *us_best = best;
+    return timed;
+}
+
 // minimal reader of the cache written below: entries of integer/float keys
 bool read_number(const std::string &obj, const char *key, double *v)
 {
@@ -132,6 +207,7 @@ int write_cache(const char *path)
     if (read_file(path, old) && arch_of(old) == arch) {
         for (const std::string &o : entry_objects(old)) {
             double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0, n1 = 0;
+            double wr = -1, wg = 0, wus = 0;
             if (!read_number(o, "n", &n) || !read_number(o, "variant", &v) ||
                 !read_number(o, "grid_mult", &g))
                 continue;
@@ -140,12 +216,20 @@ int write_cache(const char *path)
             read_number(o, "column_variant", &cv);
             read_number(o, "row_variant", &rv);
             read_number(o, "n1", &n1);
+            read_number(o, "wl_route", &wr);
+            read_number(o, "wl_grid", &wg);
+            read_number(o, "wl_us", &wus);
             bool have = false;
             for (auto &m : merged)
                 have |= m.n == (uint64_t)n;
-            if (!have)
-                merged.push_back({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
-                                  (uint64_t)n1});
+            if (!have) {
+                TunedChoice c{(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
+                              (uint64_t)n1};
+                c.wl_route = (int)wr;
+                c.wl_grid = (int)wg;
+                c.wl_us = wus;
+                merged.push_back(c);
+            }
         }
     }
     std::sort(merged.begin(), merged.end(),
@@ -159,11 +243,11 @@ int write_cache(const char *path)
         fprintf(f,
                 "    {\"n\": %llu, \"variant\": %d, \"grid_mult\": %d, \"us\": %.3f, "
                 "\"batch\": %llu, \"column_variant\": %d, \"row_variant\": %d, "
-                "\"n1\": %llu}%s\n",
+                "\"n1\": %llu, \"wl_route\": %d, \"wl_grid\": %d, \"wl_us\": %.3f}%s\n",
                 (unsigned long long)merged[i].n, merged[i].variant, merged[i].grid_mult,
                 merged[i].us, (unsigned long long)merged[i].batch, merged[i].col_variant,
-                merged[i].row_variant, (unsigned long long)merged[i].n1,
-                i + 1 < merged.size() ? "," : "");
+                merged[i].row_variant, (unsigned long long)merged[i].n1, merged[i].wl_route,
+                merged[i].wl_grid, merged[i].wl_us, i + 1 < merged.size() ? "," : "");
     fprintf(f, "  ]\n}\n");
     fclose(f);
     if (rename(tmp.c_str(), path) != 0)
@@ -263,9 +347,23 @@ extern "C" int fft_autotune(size_t segment_len, size_t batch, int direction, con
             }
         }
         (void)hipStreamSynchronize(s);
-        (void)hipStreamDestroy(s);
         (void)hipFree(in);
         (void)hipFree(out);
+        if (st == FFT_OK) {
+            // lengths with indexed work-list kernels: the work-list route too
+            int r = -1, g = 0;
+            double wus = 0;
+            const int k = tune_worklist_route(segment_len, batch, direction, s, &r, &g, &wus);
+            if (k < 0)
+                st = k;
+            else if (k > 0) {
+                choice.wl_route = r;
+                choice.wl_grid = g;
+                choice.wl_us = wus;
+                timed += k;
+            }
+        }
+        (void)hipStreamDestroy(s);
         if (st != FFT_OK)
             return st;
         set_tuned(choice);
@@ -296,25 +394,37 @@ extern "C" int fft_tune_load(const char *path)
         int k = 0;
         for (const std::string &o : entry_objects(js)) {
             double n = 0, v = 0, g = 0, us = 0, b = 0, cv = 0, rv = 0, n1 = 0;
+            double wr = -1, wg = 0, wus = 0;
             if (!read_number(o, "n", &n) || !read_number(o, "variant", &v) ||
                 !read_number(o, "grid_mult", &g))
                 continue;
             read_number(o, "column_variant", &cv);
             read_number(o, "row_variant", &rv);
             read_number(o, "n1", &n1);
+            read_number(o, "wl_route", &wr);
+            read_number(o, "wl_grid", &wg);
+            read_number(o, "wl_us", &wus);
             int ncol = 0, nrow = 0;
             if (v < 0)
                 split_variant_counts((uint64_t)n, &ncol, &nrow);
             const ColumnDesc *sc = nullptr;
             const RowDesc *sr = nullptr;
-            if (n < 1 || (v >= 0 && v >= variant_count((uint64_t)n)) || g < 0 || g > 1024 ||
+            if (n < 1 || v < -2 || (v >= 0 && v >= variant_count((uint64_t)n)) || g < 0 ||
+                g > 1024 ||
                 (v < 0 && (cv < 0 || rv < 0 || (ncol && cv >= ncol) || (nrow && rv >= nrow))) ||
                 n1 < 0 || (n1 > 0 && !find_split((uint64_t)n, &sc, &sr, 0, 0, (uint64_t)n1)))
                 continue;  // stale entry for variants this build does not have
+            const int n_idx = fft_worklist_indexed_count((uint32_t)n);
+            if (wr < -1 || wr > n_idx || wg < 0 || wg > 1024)
+                wr = -1, wg = 0;  // a work-list route this build does not have
             read_number(o, "us", &us);
             read_number(o, "batch", &b);
-            set_tuned({(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
-                       (uint64_t)n1});
+            TunedChoice c{(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
+                          (uint64_t)n1};
+            c.wl_route = (int)wr;
+            c.wl_grid = (int)wg;
+            c.wl_us = wus;
+            set_tuned(c);
             ++k;
         }
         set_ok();

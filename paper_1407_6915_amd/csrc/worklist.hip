@@ -295,6 +295,44 @@ const LengthInfo *length_info(uint32_t n)
     return nullptr;
 }
 
+// Route of a one-pass length: 0 = tiles of the work-list kernel, 1 + k =
+// a launch of its own through the k-th indexed one-pass kernel of the
+// length (its dense kernel over the listed offsets), at *grid_mult resident
+// workgroup waves per CU (0: the candidate's own).  A tuned route wins;
+// otherwise every length with an indexed kernel takes candidate 0.
+int route_of(uint32_t n, int *grid_mult)
+{
+    *grid_mult = 0;
+    int cnt = 0;
+    const SinglePassDesc *t = indexed_table(n, &cnt);
+    int g = 0;
+    const int r = tuned_wl_route(n, &g);
+    if (r == 0 || (r > 0 && r <= cnt && t[r - 1].launch_indexed)) {
+        *grid_mult = g;
+        return r;
+    }
+    return cnt > 0 && t[0].launch_indexed ? 1 : 0;
+}
+
+// Route of a two-pass length: 0 = column and row tasks of the work-list
+// kernel, 1 = the two passes over the listed segments as launches of their
+// own (the plan's tiles, indexed); tuned, else 1 where the indexed passes
+// exist.
+int route_two_pass(uint32_t n, int *grid_mult)
+{
+    *grid_mult = 0;
+    const ColumnDesc *c = nullptr;
+    const RowDesc *r = nullptr;
+    const bool have = indexed_four_step(n, &c, &r);
+    int g = 0;
+    const int t = tuned_wl_route(n, &g);
+    if (t == 0 || (t == 1 && have)) {
+        *grid_mult = g;
+        return t;
+    }
+    return have ? 1 : 0;
+}
+
 }  // namespace wl
 
 struct WorkList {
@@ -303,6 +341,7 @@ struct WorkList {
     // per-kind twiddle tables, built once
     wl::Tables *d_tables = nullptr;
     std::vector<void *> table_mem;
+    size_t table_bytes = 0;
     // the current entries
     uint64_t n_items = 0;
     uint64_t max_in = 0, max_out = 0;  // highest sample touched (+1)
@@ -313,6 +352,35 @@ struct WorkList {
     unsigned wide_grid = 1;
     const c32 *wide_tw = nullptr;        // its twiddle table (one of table_mem)
     uint64_t counts[wl::KCOUNT] = {};
+    // one-pass lengths routed to indexed launches of their own: each covers
+    // items [first, first + count) of the item array
+    struct IndexedRun {
+        const SinglePassDesc *d;
+        uint32_t kind, first, count;
+        int grid_mult;  // 0: the candidate's own
+        unsigned grid;
+        bool operator==(const IndexedRun &o) const
+        {
+            return d == o.d && kind == o.kind && first == o.first && count == o.count &&
+                   grid == o.grid;
+        }
+    };
+    std::vector<IndexedRun> indexed;
+    // the two-pass length routed to indexed passes of its own: items
+    // [first, first + count), Y at count * (n + 16) samples of d_y
+    struct IndexedTwoPass {
+        const ColumnDesc *col = nullptr;
+        const RowDesc *row = nullptr;
+        uint32_t n = 0, first = 0, count = 0;
+        int grid_mult = 0;
+        unsigned grid_a = 0, grid_b = 0;
+        bool operator==(const IndexedTwoPass &o) const
+        {
+            return col == o.col && row == o.row && n == o.n && first == o.first &&
+                   count == o.count && grid_a == o.grid_a && grid_b == o.grid_b;
+        }
+    } two_pass_idx;
+    std::vector<wl::Tables> h_tables;  // host copy of d_tables
     // planned lengths: runs of consecutive entries, and the plan they go
     // through (built for at least the longest run)
     struct PlanRun {
@@ -351,12 +419,17 @@ struct WorkList {
         const void *tasks = nullptr, *items = nullptr, *ctl = nullptr, *y = nullptr;
         const Plan *plan = nullptr;
         std::vector<PlanRun> runs;
+        std::vector<IndexedRun> indexed;
+        IndexedTwoPass two_pass_idx;
         bool operator==(const LaunchKey &o) const
         {
+            if (!(two_pass_idx == o.two_pass_idx))
+                return false;
             if (in != o.in || out != o.out || n_tasks != o.n_tasks || n_first != o.n_first ||
                 wide_first != o.wide_first || n_wide != o.n_wide || grid != o.grid ||
                 wide_grid != o.wide_grid || tasks != o.tasks || items != o.items ||
-                ctl != o.ctl || y != o.y || plan != o.plan || runs.size() != o.runs.size())
+                ctl != o.ctl || y != o.y || plan != o.plan || runs.size() != o.runs.size() ||
+                !(indexed == o.indexed))
                 return false;
             for (size_t i = 0; i < runs.size(); ++i)
                 if (runs[i].in_off != o.runs[i].in_off || runs[i].out_off != o.runs[i].out_off ||
@@ -382,6 +455,8 @@ struct WorkList {
         k.y = d_y;
         k.plan = plan;
         k.runs = plan_runs;
+        k.indexed = indexed;
+        k.two_pass_idx = two_pass_idx;
         return k;
     }
     hipGraph_t graph = nullptr;
@@ -444,6 +519,7 @@ int wl_tables(WorkList *w)
             return set_error(FFT_ERR_OUT_OF_MEMORY, "twiddle table");
         }
         w->table_mem.push_back(d);
+        w->table_bytes += v.size() * sizeof(c32);
         if ((e = hipMemcpy(d, v.data(), v.size() * sizeof(c32), hipMemcpyHostToDevice)) !=
             hipSuccess)
             return hip_error(e, "twiddle upload");
@@ -477,6 +553,7 @@ int wl_tables(WorkList *w)
             return st;
         tables[L.a].sh = sh;
     }
+    w->h_tables = tables;
     void *d = nullptr;
     hipError_t e = hipMalloc(&d, tables.size() * sizeof(Tables));
     if (e != hipSuccess) {
@@ -593,7 +670,9 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     hitems.clear();
     hitems.reserve(n);
     std::vector<Task> a_tasks, s_tasks, b_tasks;
-    std::vector<Item> wide_items;
+    std::vector<Item> wide_items, idx_items, tp_items;
+    std::vector<WorkList::IndexedRun> indexed;
+    WorkList::IndexedTwoPass tp_idx;
     std::vector<WorkList::PlanRun> plan_runs;
     uint64_t plan_len = 0, plan_max_run = 0;
     uint64_t y_samples = 0;
@@ -625,6 +704,18 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
             for (uint32_t idx : b)
                 wide_items.push_back({items[idx].in_off, items[idx].out_off, 0});
             counts[L.a] += b.size();
+        } else if (int gm = 0, r = route_two_pass(L.n, &gm); L.two_pass && r == 1) {
+            if (!b.empty()) {
+                indexed_four_step(L.n, &tp_idx.col, &tp_idx.row);
+                tp_idx.n = L.n;
+                tp_idx.count = (uint32_t)b.size();
+                tp_idx.grid_mult = gm;
+                for (uint32_t idx : b)
+                    tp_items.push_back({items[idx].in_off, items[idx].out_off, 0});
+                y_samples = std::max<uint64_t>(y_samples, b.size() * (uint64_t)(L.n + kLine));
+                counts[L.a] += b.size();
+                two_pass += (uint32_t)b.size();
+            }
         } else if (L.two_pass) {
             for (uint32_t idx : b) {
                 const uint32_t item = (uint32_t)hitems.size();
@@ -651,6 +742,14 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
                 counts[L.a] += 1;
                 ++two_pass;
             }
+        } else if (int gm = 0, r = route_of(L.n, &gm); r > 0 && !b.empty()) {
+            int cnt = 0;
+            const SinglePassDesc *d = indexed_table(L.n, &cnt) + (r - 1);
+            indexed.push_back({d, (uint32_t)L.a, (uint32_t)idx_items.size(), (uint32_t)b.size(),
+                               gm, 0});
+            for (uint32_t idx : b)
+                idx_items.push_back({items[idx].in_off, items[idx].out_off, 0});
+            counts[L.a] += b.size();
         } else {
             const size_t per_task = (size_t)L.per_tile * (size_t)L.group;
             for (size_t k = 0; k < b.size(); k += per_task) {
@@ -663,9 +762,15 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
             }
         }
     }
-    // the wide launch's items follow the task items
+    // the wide launch's items follow the task items, the indexed launches'
+    // items follow those
     const uint32_t wide_first = (uint32_t)hitems.size();
     hitems.insert(hitems.end(), wide_items.begin(), wide_items.end());
+    for (auto &r : indexed)
+        r.first += (uint32_t)hitems.size();
+    hitems.insert(hitems.end(), idx_items.begin(), idx_items.end());
+    tp_idx.first = (uint32_t)hitems.size();
+    hitems.insert(hitems.end(), tp_items.begin(), tp_items.end());
     tasks.reserve(a_tasks.size() + s_tasks.size() + b_tasks.size());
     tasks.insert(tasks.end(), a_tasks.begin(), a_tasks.end());
     tasks.insert(tasks.end(), s_tasks.begin(), s_tasks.end());
@@ -682,6 +787,8 @@ int wl_compile(WorkList *w, const fft_work_t *items, size_t n, std::vector<wl::T
     w->n_two_pass = two_pass;
     w->wide_first = wide_first;
     w->n_wide = (uint32_t)wide_items.size();
+    w->indexed.swap(indexed);
+    w->two_pass_idx = tp_idx;
     w->plan_runs.swap(plan_runs);
     w->plan_len = plan_len;
     w->plan_max_run = plan_max_run;
@@ -799,6 +906,20 @@ int wl_reset(WorkList *w, const fft_work_t *items, size_t n, hipStream_t s)
                                  kWideGridMult);
     w->grid = g;
     w->wide_grid = gw;
+    if (WorkList::IndexedTwoPass &t = w->two_pass_idx; t.count) {
+        const uint64_t n1 = (uint64_t)t.col->n1, n2 = (uint64_t)t.row->n2;
+        const int gm = t.grid_mult > 0 ? t.grid_mult : two_pass_grid_mult(n1);
+        t.grid_a = grid_for(t.col->kernel_indexed[w->dir > 0], t.col->threads * t.col->cols,
+                            t.count * (n2 / (uint64_t)t.col->cols), w->device, gm);
+        t.grid_b = grid_for(t.row->kernel_indexed[w->dir > 0], t.row->threads * t.row->rows,
+                            t.count * (n1 / (uint64_t)t.row->rows), w->device, gm);
+    }
+    for (auto &r : w->indexed) {
+        const SinglePassDesc *d = r.d;
+        const uint64_t groups = (r.count + d->segs_per_wg - 1) / d->segs_per_wg;
+        r.grid = grid_for(d->kernel_indexed[w->dir > 0], d->threads * d->segs_per_wg, groups,
+                          w->device, r.grid_mult > 0 ? r.grid_mult : d->grid_mult);
+    }
     w->ready = true;
     return set_ok();
 }
@@ -814,8 +935,24 @@ int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
         if (st != FFT_OK)
             return st;
     }
-    if (w->n_tasks == 0 && w->n_wide == 0)
-        return set_ok();
+    // the two-pass length with passes of its own: A, then B
+    if (const WorkList::IndexedTwoPass &t = w->two_pass_idx; t.count) {
+        const wl::Tables &ta = w->h_tables[wl::K65536A], &tb = w->h_tables[wl::K65536B];
+        const uint64_t *offs = reinterpret_cast<const uint64_t *>(w->d_items + t.first);
+        t.col->launch_indexed(w->dir, in, w->d_y, ta.tw, ta.tl, ta.th, ta.sh, t.row->n2, offs,
+                              t.count, t.grid_a, s);
+        t.row->launch_indexed(w->dir, in, w->d_y, out, tb.tw, t.col->n1, offs, t.count,
+                              t.grid_b, s);
+    }
+    // one-pass lengths with launches of their own
+    for (const WorkList::IndexedRun &r : w->indexed)
+        r.d->launch_indexed(w->dir, in, out, w->h_tables[r.kind].tw,
+                            reinterpret_cast<const uint64_t *>(w->d_items + r.first), r.count,
+                            r.grid, s);
+    if (w->n_tasks == 0 && w->n_wide == 0) {
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? set_ok() : hip_error(e, "indexed launch");
+    }
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, w->d_ctl, 2u);
     // launch 0: pass-A and single-pass tasks; then the wide tiles; launch 1:
     // pass-B tasks
@@ -850,6 +987,22 @@ int wl_enqueue(WorkList *w, const void *in, void *out, hipStream_t s)
     return set_ok();
 }
 
+// device memory the work list holds now: its arrays at their capacities,
+// the two-pass scratch, the twiddle tables and the four-step plan's
+// scratch and tables
+size_t wl_device_bytes(const WorkList *w)
+{
+    size_t b = w->cap_tasks * sizeof(wl::Task) + w->cap_items * sizeof(wl::Item) +
+               w->cap_ctl * sizeof(uint32_t) + w->cap_y * sizeof(c32) + w->table_bytes +
+               wl::KCOUNT * sizeof(wl::Tables);
+    if (w->plan) {
+        const Plan *p = w->plan;
+        const uint64_t lo = 1ull << p->sh;
+        b += p->scratch_bytes + (p->n1 + p->n2 + lo + (p->n + lo - 1) / lo) * sizeof(c32);
+    }
+    return b;
+}
+
 int wl_check_io(WorkList *w, const void *in, void *out)
 {
     if (!in || !out)
@@ -859,7 +1012,8 @@ int wl_check_io(WorkList *w, const void *in, void *out)
     if (!w->ready)
         return set_error(FFT_ERR_INVALID_ARG,
                          "the last reset failed after taking its entries: reset again");
-    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
+    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty() && w->indexed.empty() &&
+        !w->two_pass_idx.count)
         return FFT_OK;
     if (in == out && !w->in_place_ok)
         return set_error(FFT_ERR_OVERLAP,
@@ -960,7 +1114,8 @@ extern "C" int fft_worklist_exec_graph(fft_worklist_t wlh, const void *in_base, 
     int st = wl_check_io(w, in_base, out_base);
     if (st != FFT_OK)
         return st;
-    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty())
+    if (w->n_tasks == 0 && w->n_wide == 0 && w->plan_runs.empty() && w->indexed.empty() &&
+        !w->two_pass_idx.count)
         return set_ok();
     hipError_t e;
     WorkList::LaunchKey k = w->key(in_base, out_base);
@@ -1026,8 +1181,11 @@ extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
                      ",\"wide_segments\":" + std::to_string(w->n_wide) +
                      ",\"wide_grid\":" + std::to_string(w->wide_grid) +
                      ",\"plan_runs\":" + std::to_string(w->plan_runs.size()) +
+                     ",\"indexed_launches\":" + std::to_string(w->indexed.size()) +
+                     ",\"indexed_two_pass_segments\":" + std::to_string(w->two_pass_idx.count) +
                      ",\"samples\":" + std::to_string(w->samples) +
                      ",\"scratch_bytes\":" + std::to_string(w->y_bytes) +
+                     ",\"device_bytes\":" + std::to_string(wl_device_bytes(w)) +
                      ",\"in_place_ok\":" + (w->in_place_ok ? "true" : "false") +
                      ",\"grid\":" + std::to_string(w->grid) + ",\"segments_per_length\":{";
     bool first = true;
@@ -1036,6 +1194,15 @@ extern "C" int fft_worklist_describe(fft_worklist_t wlh, char *buf, size_t len)
             continue;
         js += std::string(first ? "" : ",") + "\"" + std::to_string(L.n) +
               "\":" + std::to_string(w->counts[L.a]);
+        first = false;
+    }
+    js += "},\"indexed\":{";
+    first = true;
+    for (const WorkList::IndexedRun &r : w->indexed) {
+        js += std::string(first ? "" : ",") + "\"" + std::to_string(r.d->n) +
+              "\":{\"candidate\":" + std::to_string(r.d->variant) +
+              ",\"segments\":" + std::to_string(r.count) + ",\"grid\":" +
+              std::to_string(r.grid) + "}";
         first = false;
     }
     js += "}}";
@@ -1123,6 +1290,22 @@ extern "C" int fft_worklist_cache_clear(void)
         delete c.w;
     g_cache.clear();
     return set_ok();
+}
+
+extern "C" int fft_worklist_indexed_count(uint32_t segment_len)
+{
+    set_ok();
+    const wl::LengthInfo *li = wl::length_info(segment_len);
+    if (li && li->two_pass && !li->planned) {
+        const ColumnDesc *c = nullptr;
+        const RowDesc *r = nullptr;
+        return indexed_four_step(segment_len, &c, &r) ? 1 : 0;
+    }
+    if (!li || li->two_pass || li->wide || li->planned)
+        return 0;
+    int cnt = 0;
+    (void)indexed_table(segment_len, &cnt);
+    return cnt;
 }
 
 extern "C" int fft_worklist_supported(uint32_t segment_len)

@@ -148,20 +148,30 @@ class GpuExecutor:
     three torch streams (copy in, transform, copy out), one reusable work
     list re-filled for every packed launch."""
 
-    def __init__(self, arena_samples: int, direction: int = FORWARD, device: str = "cuda",
-                 max_launch_samples: int = 0):
+    def __init__(self, arena_samples: int = 0, direction: int = FORWARD, device: str = "cuda",
+                 max_launch_samples: int = 0, hbm_budget_bytes: int = 0):
+        """arena_samples: size of the job arena; or hbm_budget_bytes: the
+        whole device footprint allowed, of which the arena gets what the
+        work list's reserved arrays, scratch and plan leave."""
         import torch
         from . import WorkList
         self.torch = torch
         self.dev = torch.device(device)
-        self.arena = torch.empty(arena_samples, dtype=torch.complex64, device=self.dev)
-        self.base = self.arena.data_ptr()
         self.s_in = torch.cuda.Stream(self.dev)
         self.s_comp = torch.cuda.Stream(self.dev)
         self.s_out = torch.cuda.Stream(self.dev)
         self.wl = WorkList((), direction)
         if max_launch_samples:
             self.reserve(max_launch_samples)
+        self.resident_bytes = int(self.wl.describe().get("device_bytes", 0))
+        if hbm_budget_bytes:
+            arena_samples = (hbm_budget_bytes - self.resident_bytes) // SAMPLE_BYTES
+            if arena_samples <= 0:
+                raise ValueError("the work list's %d resident bytes exceed the budget"
+                                 % self.resident_bytes)
+        self.arena_samples = int(arena_samples)
+        self.arena = torch.empty(self.arena_samples, dtype=torch.complex64, device=self.dev)
+        self.base = self.arena.data_ptr()
         self.t0 = time.perf_counter()
         self.launches: List[List[int]] = []
         self.max_launch_samples = 0

@@ -95,3 +95,31 @@ def test_overlap_summary_from_traces(tmp_path):
     # H2D 10-20 overlaps D2H 14-24 for 6 of the 20 ms
     assert "H2D time with a D2H in flight: 30.0 %" in text
     assert "device idle (no copy and no transform): 0.0 ms" in text
+
+
+def test_traffic_table_per_sample(tmp_path):
+    copy_samples = 1 << 20
+    known_kib = copy_samples * 8 / 1024
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    # FETCH_SIZE counts half of the bytes read, WRITE_SIZE all of them
+    _counter_csv(fp, "FETCH_SIZE", [("identity_copy_kernel<x>", known_kib / 2),
+                                    ("four_step_columns_kernel<a>", known_kib / 2 / 4),
+                                    ("four_step_columns_kernel<a>", known_kib / 2 / 4),
+                                    ("single_pass_plain_kernel<b>", known_kib / 2 * 1.5)])
+    _counter_csv(wp, "WRITE_SIZE", [("identity_copy_kernel<x>", known_kib),
+                                    ("four_step_columns_kernel<a>", known_kib / 4),
+                                    ("four_step_columns_kernel<a>", known_kib / 4),
+                                    ("single_pass_plain_kernel<b>", known_kib)])
+    out = tmp_path / "t.json"
+    bench_profile.traffic_table(str(fp), str(wp), str(out), copy_samples,
+                                [("four_step", copy_samples // 4),
+                                 ("single_pass", copy_samples)])
+    t = json.load(open(out))
+    rows = {r["kernel"]: r for r in t["kernels"]}
+    col = rows["four_step_columns_kernel<a>"]
+    assert col["dispatches"] == 2
+    assert abs(col["hbm_read_bytes_per_sample"] - 8.0) < 1e-9
+    assert abs(col["hbm_write_bytes_per_sample"] - 8.0) < 1e-9
+    sp = rows["single_pass_plain_kernel<b>"]
+    assert abs(sp["hbm_read_bytes_per_sample"] - 12.0) < 1e-9
+    assert abs(sp["hbm_bytes_per_sample"] - 20.0) < 1e-9

@@ -45,11 +45,25 @@ def test_autotune_and_cache(tmp_path):
     path = str(tmp_path / "tune.json")
     fs.tune_clear()
     k, best = fs.autotune(4096, 8192, fs.FORWARD, path)
-    assert k == fs.variant_count(4096) * 6 and best > 0
+    # every plan variant at 6 grids, then the work-list routes: the tiles
+    # once, each indexed kernel at 6 grids
+    assert k == fs.variant_count(4096) * 6 + 1 + 6 * fs.indexed_count(4096) and best > 0
     js = json.load(open(path))
     ent = [e for e in js["entries"] if e["n"] == 4096]
     assert len(ent) == 1 and 0 <= ent[0]["variant"] < fs.variant_count(4096)
+    assert 0 <= ent[0]["wl_route"] <= fs.indexed_count(4096) and ent[0]["wl_us"] > 0
     assert js["arch"].startswith("gfx")
+    # a work list built now takes the tuned route for its 4096-point segments
+    ents = np.zeros(20, dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                               ("segment_len", "<u4"), ("job", "<u4")])
+    ents["in_off"] = ents["out_off"] = np.arange(20) * 4099
+    ents["segment_len"] = 4096
+    with fs.WorkList(ents) as wl:
+        idx = wl.describe()["indexed"]
+        if ent[0]["wl_route"] == 0:
+            assert idx == {}
+        else:
+            assert idx["4096"]["candidate"] == ent[0]["wl_route"] - 1
     # a tuned plan reports the chosen variant and grid, and stays correct
     d = fs.Plan(4096, 64).describe()
     assert d["variant"] == ent[0]["variant"] and d["grid_mult"] == ent[0]["grid_mult"]
@@ -63,7 +77,8 @@ def test_autotune_and_cache(tmp_path):
     # 512 x 128); merged into the same file
     n1, n2, nc, nr = fs.split_info(1 << 16)
     k2, _ = fs.autotune(1 << 16, 64, fs.FORWARD, path)
-    assert k2 == 6 * (nc * nr + 2)
+    # plus the work-list routes: the tiles once, the indexed passes at 6 grids
+    assert k2 == 6 * (nc * nr + 2) + 1 + 6 * fs.indexed_count(1 << 16)
     js = json.load(open(path))
     assert {e["n"] for e in js["entries"]} == {4096, 1 << 16}
     e2 = [e for e in js["entries"] if e["n"] == 1 << 16][0]

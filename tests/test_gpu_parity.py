@@ -46,9 +46,16 @@ def test_small_workload_all_segments():
     idx = np.random.default_rng(0).choice(b, 64, replace=False)
     ref = oracle.dft_direct(x[idx], n)
     assert np.all(oracle.rel_l2(y[idx], ref) <= oracle.tolerance(n))
-    # the three unit tones stand out as spikes of height ~N in every segment
-    for b0, _, _ in workloads.small_signal().tones:
-        assert np.all(np.abs(y[:, b0]) > 0.9 * n)
+    # the three unit tones (phase 0) give N at their bins in every segment,
+    # plus the noise's share of that bin (complex std sqrt(2N) = 45): their
+    # mean over the 1024 segments is N within 2 % (about 14 standard
+    # deviations of that mean), and the other bins average near 0
+    tone_bins = [b0 for b0, _, _ in workloads.small_signal().tones]
+    mean = y.astype(np.complex128).mean(axis=0)
+    for b0 in tone_bins:
+        assert abs(mean[b0] - n) < 0.02 * n, (b0, mean[b0])
+    others = np.delete(np.abs(mean), tone_bins)
+    assert others.max() < 0.02 * n
 
 
 @pytest.mark.parametrize("n", SINGLE + FOUR_STEP + FALLBACK)

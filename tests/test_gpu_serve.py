@@ -67,10 +67,16 @@ def test_alone_equals_mix_and_matches_oracle():
 
 
 def test_reserved_capacity_then_serving():
-    announce("serving: reserved work-list capacity")
+    announce("serving: reserved work-list capacity inside an HBM budget")
     jobs, keep = make_jobs(8, seed_offset=11)
-    arena = sum(j.samples for j in jobs) + 64 * len(jobs)
-    ex = GpuExecutor(arena, max_launch_samples=1 << 22)
+    need = sum(j.samples for j in jobs) + 64 * len(jobs)
+    budget = need * 8 + (1 << 30)
+    ex = GpuExecutor(max_launch_samples=1 << 22, hbm_budget_bytes=budget)
+    # the reserved work list (arrays, two-pass scratch, the 2^20-point
+    # plan) counts against the budget; the arena gets the rest
+    assert ex.resident_bytes > (1 << 22) * 8
+    assert 0 <= budget - (ex.arena_samples * 8 + ex.resident_bytes) < 8
+    arena = ex.arena_samples
     st = serve(jobs, ex, arena, max_launch_samples=1 << 22)
     assert st["completed"] + st["rejected"] == len(jobs)
     for j in jobs:

@@ -16,6 +16,28 @@ pytestmark = pytest.mark.gpu
 LENGTHS = [256, 1000, 1024, 1536, 4096, 6000, 16384, 65536]
 
 
+class routes:
+    """Work-list routes forced through a tuning cache: {length: route}, 0 =
+    the work-list kernel's tiles, 1 + k = the k-th indexed one-pass kernel
+    (grid: its own).  Cleared on exit."""
+
+    def __init__(self, table, tmp_path):
+        self.table, self.path = table, str(tmp_path / "routes.json")
+
+    def __enter__(self):
+        import json
+        import torch
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        ents = [{"n": n, "variant": -2, "grid_mult": 0, "wl_route": r, "wl_grid": 0}
+                for n, r in self.table.items()]
+        json.dump({"arch": arch, "entries": ents}, open(self.path, "w"))
+        assert fs.tune_load(self.path) == len(ents)
+        return self
+
+    def __exit__(self, *exc):
+        fs.tune_clear()
+
+
 def packed(lengths, gap=0, seed=0):
     """Back-to-back layout in list order (optionally with gaps); returns
     in offsets, out offsets (a different permutation of slots) and total."""
@@ -299,7 +321,50 @@ def test_uneven_workload_full_size():
     print("  sampled 16 per length, worst error / bound %.3f" % worst, flush=True)
 
 
-def test_graph_recaptured_when_a_reset_changes_launch_arguments():
+@pytest.mark.parametrize("route", [0, 1, 2])
+def test_one_pass_routes(route, tmp_path):
+    """Every one-pass length through the work-list kernel's tiles (0), its
+    default indexed kernel (1) or its second indexed kernel (2, where the
+    length has one): every segment against the oracle, eager and graph."""
+    import torch
+    one_pass = [256, 1000, 1024, 1536, 4096, 6000]
+    rng = np.random.default_rng(30 + route)
+    lengths = np.array(rng.choice(LENGTHS, 50).tolist() + LENGTHS, np.int64)
+    rng.shuffle(lengths)
+    in_off, total = packed(lengths, gap=5)
+    out_off, out_total = packed(lengths[::-1], gap=1)
+    out_off = out_off[::-1].copy()
+    announce("work list routes=%d, %d segments" % (route, len(lengths)))
+    x = siggen.Signal(seed=31, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(out_total, dtype=torch.complex64, device="cuda")
+    # 65536: its tasks (route 0) or its indexed passes (routes 1, 2 -> 1)
+    table = {n: route for n in one_pass}
+    table[65536] = min(route, 1)
+    with routes(table, tmp_path):
+        with fs.WorkList(to_entries(in_off, out_off, lengths)) as wl:
+            d = wl.describe()
+            assert d["indexed_two_pass_segments"] == (0 if route == 0 else
+                                                      int((lengths == 65536).sum()))
+            if route == 0:
+                assert d["indexed_launches"] == 0
+            else:
+                assert set(d["indexed"]) == {str(n) for n in one_pass}
+                for n in one_pass:
+                    want = route - 1 if route - 1 < fs.indexed_count(n) else 0
+                    assert d["indexed"][str(n)]["candidate"] == want
+            wl.exec(xd, yd)
+            wl.status()
+            y = yd.cpu().numpy()
+            check_all(x, y, in_off, out_off, lengths)
+            for _ in range(2):
+                yd.zero_()
+                wl.exec(xd, yd, graph=True)
+                wl.status()
+                assert np.array_equal(yd.cpu().numpy(), y)
+
+
+def test_graph_recaptured_when_a_reset_changes_launch_arguments(tmp_path):
     """The graph's launches hold the task counts and splits, the wide range
     and the grids as fixed arguments.  Resets that keep the planned runs and
     the grid but change those must not replay the old graph: (1) a 4096-point
@@ -336,7 +401,9 @@ def test_graph_recaptured_when_a_reset_changes_launch_arguments():
     x = siggen.Signal(seed=19, seg_len=1, sigma=1.0).samples(0, total)
     xd = torch.from_numpy(x).cuda()
     yd = torch.zeros(total, dtype=torch.complex64, device="cuda")
-    with fs.WorkList(to_entries(o1, o1, l1)) as wl:
+    # the 256- and 65536-point segments as work-list tasks (not launches
+    # of their own)
+    with routes({256: 0, 65536: 0}, tmp_path), fs.WorkList(to_entries(o1, o1, l1)) as wl:
         d1 = wl.describe()
         wl.exec(xd, yd, graph=True)
         wl.status()
