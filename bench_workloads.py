@@ -99,6 +99,27 @@ def uneven(args):
     desc_t = wl.describe()
     wl.close()
     fs.tune_clear()
+    # reference from the packed layout: per length, gather its segments into
+    # a contiguous batch, one plain launch, scatter the spectra back (every
+    # length here is a multiple of 8 samples, so the gather moves 64-byte
+    # rows)
+    rows8 = {}
+    for n in workloads.UNEVEN_LENGTHS:
+        sel = torch.from_numpy(in_off[lengths == n].astype(np.int64) // 8).cuda()
+        rows8[n] = (sel[:, None] + torch.arange(n // 8, device="cuda")[None, :]).reshape(-1)
+    gplans = {n: fs.Plan(n, int((lengths == n).sum())) for n in workloads.UNEVEN_LENGTHS}
+    xv, yv = xd.view(-1, 8), yd.view(-1, 8)
+
+    def gather_plain_scatter():
+        for n, idx in rows8.items():
+            xs = xv.index_select(0, idx)
+            ys = torch.empty_like(xs)
+            gplans[n].exec_ptr(xs.data_ptr(), ys.data_ptr(), sh)
+            yv.index_copy_(0, idx, ys)
+    t_gps = _time(torch, gather_plain_scatter, max(3, args.steps // 3))
+    for p in gplans.values():
+        p.close()
+    del rows8, xv, yv
     # reference: one plain batched launch per length over length-sorted data
     per_len = {}
     bufs = {}
@@ -127,6 +148,9 @@ def uneven(args):
                      "indexed": desc_t.get("indexed"), "tune_s": round(t_tune, 1),
                      "best_us_per_length": tuned},
            "per_length_plain_ms": round(t_plain * 1e3, 3), "per_length_ms": per_len,
+           "per_length_from_packed_ms": round(t_gps * 1e3, 3),
+           "per_length_from_packed_note": "gather each length's segments (index_select of "
+                                         "64-byte rows), one plain launch, scatter back",
            "GFLOP/s": {"persistent": round(flops / t_wl / 1e9, 1),
                        "persistent_graph": round(flops / t_graph / 1e9, 1),
                        "per_length_plain": round(flops / t_plain / 1e9, 1)},

@@ -307,7 +307,7 @@ int fft_worklist_supported(uint32_t segment_len);
  * one-pass kernels; 65536: 1, its two passes as launches of their own; 0
  * for 16384, 2^20 and unsupported lengths.  Route 0 is the tiles, route
  * 1 + k the k-th indexed kernel; fft_autotune picks one per length,
- * untuned lengths take route 1. */
+ * untuned one-pass lengths take route 1, untuned 65536 route 0. */
 int fft_worklist_indexed_count(uint32_t segment_len);
 
 /* Compile n entries into workgroup tasks: segments are grouped by length,

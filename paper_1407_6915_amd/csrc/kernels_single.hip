@@ -89,10 +89,8 @@ const SinglePassDesc kTable[] = {
     // cached loads and stores (stage 0 reads 375-sample runs that straddle
     // lines; streamed loads fetch the shared lines twice)
     SpInst<6000, 400, 1, 4, kClassic, 16, 15, 25>::desc(5, 32),
-    // radix 15 or 25 first: stage 0 reads at strides of 400 or 240 samples,
-    // whole lines
-    SpInst<6000, 400, 1, 4, kClassic | kNT, 15, 25, 16>::desc(6, 32),
-    SpInst<6000, 400, 1, 4, kClassic | kNT, 25, 15, 16>::desc(7, 32),
+    // radix 25 first: stage 0 reads at a stride of 240 samples, whole lines
+    SpInst<6000, 400, 1, 4, kClassic | kNT, 25, 15, 16>::desc(6, 32),
 };
 
 }  // namespace

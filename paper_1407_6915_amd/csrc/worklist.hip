@@ -316,8 +316,9 @@ int route_of(uint32_t n, int *grid_mult)
 
 // Route of a two-pass length: 0 = column and row tasks of the work-list
 // kernel, 1 = the two passes over the listed segments as launches of their
-// own (the plan's tiles, indexed); tuned, else 1 where the indexed passes
-// exist.
+// own (the plan's tiles, indexed).  Tuned, else 0: on the uneven workload
+// (65536-point segments packed at unaligned offsets among others) the
+// tasks took 12.1 ms and the indexed passes 13.7.
 int route_two_pass(uint32_t n, int *grid_mult)
 {
     *grid_mult = 0;
@@ -330,7 +331,7 @@ int route_two_pass(uint32_t n, int *grid_mult)
         *grid_mult = g;
         return t;
     }
-    return have ? 1 : 0;
+    return 0;
 }
 
 }  // namespace wl
