@@ -218,6 +218,8 @@ def main():
                     help="large = the 4096-point x 262144 batch (the reported metric); "
                          "the others print their own JSON line")
     ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uneven: skip the autotuned run (for profiling the default one)")
     ap.add_argument("--lengths", default="16384,6000,4096,1000",
                     help="lengths: segment lengths to time, 8 GiB each")
     ap.add_argument("--file-gib", type=int, default=16,

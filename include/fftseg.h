@@ -174,9 +174,12 @@ size_t fft_plan_scratch_bytes(fft_plan_t plan);
 
 /* Producer: write chunk `chunk` (bytes = plan batch * segment_len * 8) into
  * the library's pinned host slot `dst`.  Return 0 on success.  Called from
- * the thread that called fft_exec_stream. */
+ * the thread that called fft_exec_stream, in chunk order. */
 typedef int (*fft_fill_fn)(void *user, uint64_t chunk, void *dst, uint64_t bytes);
-/* Consumer: read the spectra of chunk `chunk` from pinned slot `src`. */
+/* Consumer: read the spectra of chunk `chunk` from pinned slot `src`.
+ * Called in chunk order from a worker thread of the library, at the same
+ * time as fill works on later chunks: `user` state that both touch must
+ * allow that. */
 typedef int (*fft_drain_fn)(void *user, uint64_t chunk, const void *src,
                             uint64_t bytes);
 

@@ -11,7 +11,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <vector>
 
 namespace fftseg {
@@ -250,32 +254,74 @@ extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn f
         Pipeline pl;
         if ((st = pl.init(p, std::max(n_slots, kDevSlots) + 1, &S->timeline)) != FFT_OK)
             return st;
-        const uint64_t lag = (uint64_t)n_slots - 1;  // chunks in flight before a drain
-        uint64_t drained = 0;
+        // The drain side runs on a worker thread: it waits for each chunk's
+        // copy out, hands the chunk to drain and frees its output slot, in
+        // chunk order, while this thread fills and issues later chunks, so
+        // host work on both sides overlaps.  Chunk c reuses the slots of
+        // chunk c - n_slots once that chunk's input has left host memory
+        // and its output has been drained.
+        struct Shared {
+            std::mutex mu;
+            std::condition_variable cv;
+            uint64_t issued = 0, drained = 0;
+            bool done_issuing = false;
+            bool failed = false;  // the worker stopped at fail_at
+            uint64_t fail_at = UINT64_MAX;
+            int code = FFT_OK;
+            std::string msg;
+        } sh;
+        std::thread worker([&] {
+            for (uint64_t c = 0;; ++c) {
+                {
+                    std::unique_lock<std::mutex> lk(sh.mu);
+                    sh.cv.wait(lk, [&] { return c < sh.issued || sh.done_issuing; });
+                    if (c >= sh.issued)
+                        return;
+                }
+                int s2 = pl.wait_chunk(c, stats);
+                if (s2 == FFT_OK && drain) {
+                    const double t0 = now_s();
+                    const int rc = drain(user, c, S->ring.out[c % n_slots], bytes);
+                    if (stats)
+                        stats->drain_s += now_s() - t0;
+                    if (rc != 0)
+                        s2 = set_error(FFT_ERR_CALLBACK, "drain callback returned %d at chunk %llu",
+                                       rc, (unsigned long long)c);
+                }
+                std::lock_guard<std::mutex> lk(sh.mu);
+                if (s2 != FFT_OK) {
+                    // status and message are thread-local: carry them over
+                    sh.failed = true;
+                    sh.fail_at = c;
+                    sh.code = last_status();
+                    sh.msg = last_message();
+                    sh.cv.notify_all();
+                    return;
+                }
+                sh.drained = c + 1;
+                if (stats)
+                    stats->chunks_done = c + 1;
+                sh.cv.notify_all();
+            }
+        });
         int fail = FFT_OK;
         uint64_t fail_at = UINT64_MAX;
-        auto drain_one = [&](uint64_t c) -> int {
-            int s2 = pl.wait_chunk(c, stats);
-            if (s2 != FFT_OK)
-                return s2;
-            if (drain) {
-                const double t0 = now_s();
-                const int rc = drain(user, c, S->ring.out[c % n_slots], bytes);
-                if (stats)
-                    stats->drain_s += now_s() - t0;
-                if (rc != 0)
-                    return set_error(FFT_ERR_CALLBACK, "drain callback returned %d at chunk %llu",
-                                     rc, (unsigned long long)c);
-            }
-            if (stats)
-                stats->chunks_done = c + 1;
-            return FFT_OK;
-        };
+        std::string fail_msg;
         for (uint64_t c = 0; c < n_chunks; ++c) {
-            if (c >= (uint64_t)n_slots && (st = pl.wait_input_consumed(c - n_slots)) != FFT_OK) {
-                fail = st;
-                fail_at = c;
-                break;
+            if (c >= (uint64_t)n_slots) {
+                if ((st = pl.wait_input_consumed(c - n_slots)) != FFT_OK) {
+                    fail = st;
+                    fail_at = c;
+                    fail_msg = last_message();
+                    break;
+                }
+                std::unique_lock<std::mutex> lk(sh.mu);
+                sh.cv.wait(lk, [&] { return sh.drained > c - n_slots || sh.failed; });
+            }
+            {
+                std::lock_guard<std::mutex> lk(sh.mu);
+                if (sh.failed)
+                    break;
             }
             const double t0 = now_s();
             const int rc = fill(user, c, S->ring.in[c % n_slots], bytes);
@@ -285,53 +331,43 @@ extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn f
                 fail = set_error(FFT_ERR_CALLBACK, "fill callback returned %d at chunk %llu", rc,
                                  (unsigned long long)c);
                 fail_at = c;
+                fail_msg = last_message();
                 break;
             }
             if ((st = pl.issue(c, S->ring.in[c % n_slots], S->ring.out[c % n_slots])) != FFT_OK) {
                 fail = st;
                 fail_at = c;
+                fail_msg = last_message();
                 break;
             }
-            if (c >= lag) {
-                if ((st = drain_one(drained)) != FFT_OK) {
-                    fail = st;
-                    fail_at = drained;
-                    break;
-                }
-                ++drained;
-            }
+            std::lock_guard<std::mutex> lk(sh.mu);
+            sh.issued = c + 1;
+            sh.cv.notify_all();
         }
-        // finish what was issued before any failure
-        const uint64_t issued_end = fail == FFT_OK ? n_chunks : fail_at;
-        while (fail == FFT_OK && drained < issued_end) {
-            if ((st = drain_one(drained)) != FFT_OK) {
-                fail = st;
-                fail_at = drained;
-                break;
-            }
-            ++drained;
+        {
+            // the worker drains every chunk issued (or stops at a failure)
+            std::lock_guard<std::mutex> lk(sh.mu);
+            sh.done_issuing = true;
+            sh.cv.notify_all();
         }
+        worker.join();
         (void)hipStreamSynchronize(pl.s_in);
         (void)hipStreamSynchronize(pl.s_comp);
         (void)hipStreamSynchronize(pl.s_out);
-        if (fail != FFT_OK) {
-            // chunks below the failing one are handed out; a drain that
-            // fails on the way becomes the reported failure
-            while (drained < fail_at) {
-                if (drain_one(drained) != FFT_OK) {
-                    fail_at = drained;
-                    break;
-                }
-                ++drained;
-            }
-            if (failed_chunk)
-                *failed_chunk = fail_at;
-            if (stats)
-                stats->wall_s = now_s() - t_start;
-            return last_status();
-        }
         if (stats)
             stats->wall_s = now_s() - t_start;
+        // a drain that failed below the chunk this thread stopped at is the
+        // reported failure; chunks below the reported one were handed out
+        if (sh.failed && sh.fail_at < fail_at) {
+            fail = sh.code;
+            fail_at = sh.fail_at;
+            fail_msg = sh.msg;
+        }
+        if (fail != FFT_OK) {
+            if (failed_chunk)
+                *failed_chunk = fail_at;
+            return set_error(fail, "%s", fail_msg.c_str());
+        }
         return set_ok();
     } catch (...) {
         return set_error(FFT_ERR_OUT_OF_MEMORY, "host allocation failed");

@@ -64,6 +64,7 @@ class _CChunkSource(ctypes.Structure):
         ("energy_in", ctypes.c_void_p),
         ("energy_out", ctypes.c_void_p),
         ("saved_out", ctypes.c_void_p),
+        ("drain_threads", ctypes.c_int),
     ]
 
 
@@ -208,13 +209,14 @@ class Signal:
         return addr, src
 
     def checked_chunk_source(self, chunk_segments: int, n_chunks: int,
-                             first_seg: int = 0, threads: int = 0):
+                             first_seg: int = 0, threads: int = 0, drain_threads: int = 0):
         """Producer and consumer for streaming n_chunks chunks of
         chunk_segments whole segments (chunk c = segments first_seg +
         c*chunk_segments ..).  The producer records every segment's input
         energy, the consumer every segment's output energy and a copy of the
-        first and last segment of each chunk.  Returns (fill address, drain
-        address, user struct, CheckedStream with the arrays)."""
+        first and last segment of each chunk (its sums on drain_threads
+        threads, <= 0: threads).  Returns (fill address, drain address,
+        user struct, CheckedStream with the arrays)."""
         n = self.seg_len
         chk = CheckedStream(
             energy_in=np.zeros((n_chunks, chunk_segments), np.float64),
@@ -223,7 +225,8 @@ class Signal:
         cs, keep = self._c()
         src = _CChunkSource(cs, first_seg * n, chunk_segments * n, threads, n,
                             n_chunks, chk.energy_in.ctypes.data,
-                            chk.energy_out.ctypes.data, chk.saved_out.ctypes.data)
+                            chk.energy_out.ctypes.data, chk.saved_out.ctypes.data,
+                            drain_threads)
         src._keep = (keep, chk)
         L = _load()
         fill = ctypes.cast(L.sg_fill_chunk, ctypes.c_void_p).value

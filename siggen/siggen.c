@@ -712,7 +712,11 @@ void sg_test_turn(uint64_t num, uint64_t den, double out[2])
  * length), the producer records each segment's input energy and the
  * consumer each segment's output energy, for a Parseval check of every
  * segment, and the consumer keeps a copy of the first and last segment of
- * every chunk (saved_out: 2 segments per chunk) for spot checks.
+ * every chunk (saved_out: 2 segments per chunk) for spot checks.  A
+ * streaming library may call the consumer on another thread while the
+ * producer fills later chunks: the two write disjoint parts of the arrays,
+ * and drain_threads keeps the consumer's memory-bound sums from taking
+ * every core from the producer.
  */
 typedef struct {
     sg_signal sig;
@@ -724,6 +728,7 @@ typedef struct {
     double *energy_in;        /* [n_chunks * segs per chunk] or NULL    */
     double *energy_out;       /* [n_chunks * segs per chunk] or NULL    */
     float *saved_out;         /* [n_chunks * 2 * check_seg_len * 2] or NULL */
+    int drain_threads;        /* threads of the consumer's sums (<= 0: threads) */
 } sg_chunk_source;
 
 int sg_fill_chunk(void *user, uint64_t chunk, void *dst, uint64_t bytes)
@@ -757,7 +762,8 @@ int sg_drain_chunk(void *user, uint64_t chunk, const void *src_buf, uint64_t byt
     const uint64_t spc = src->chunk_samples / L;
     const float *y = (const float *)src_buf;
     if (src->energy_out &&
-        sg_energy(y, spc, L, src->energy_out + chunk * spc, src->threads) != 0)
+        sg_energy(y, spc, L, src->energy_out + chunk * spc,
+                  src->drain_threads > 0 ? src->drain_threads : src->threads) != 0)
         return -2;
     if (src->saved_out) {
         float *keep = src->saved_out + chunk * 2 * L * 2;
