@@ -44,10 +44,45 @@ def small(args):
     with fs.Plan(n, b) as p:
         t = _time(torch, lambda: p.exec_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
         tg = _time(torch, lambda: p.exec_graph_ptr(xd.data_ptr(), yd.data_ptr(), sh), args.steps)
+    # where a graph pays: launch sequences, small enough that launching
+    # them costs more than running them: a two-pass plan of 16 segments of
+    # 65536 points split into 2-segment sub-batches (16 launches), and a
+    # small mixed work list (8 segments of each length: one launch per
+    # one-pass length, the wide tiles, the two work-list launches)
+    import os
+    seqs = {}
+    m = 1 << 16
+    xm = torch.randn(16 * m, dtype=torch.complex64, device="cuda")
+    ym = torch.empty_like(xm)
+    os.environ["FFTSEG_SUB_SAMPLES"] = str(2 * m)
+    try:
+        with fs.Plan(m, 16) as p:
+            te = _time(torch, lambda: p.exec_ptr(xm.data_ptr(), ym.data_ptr(), sh), args.steps)
+            tgr = _time(torch, lambda: p.exec_graph_ptr(xm.data_ptr(), ym.data_ptr(), sh),
+                        args.steps)
+    finally:
+        del os.environ["FFTSEG_SUB_SAMPLES"]
+    seqs["plan_65536x16_in_8_sub_batches"] = {"launches": 16, "us_per_exec": round(te * 1e6, 2),
+                                              "us_per_graph_exec": round(tgr * 1e6, 2)}
+    lens = np.repeat(np.asarray(workloads.UNEVEN_LENGTHS, np.int64), 8)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    ent = np.zeros(len(lens), dtype=[("in_off", "<u8"), ("out_off", "<u8"),
+                                     ("segment_len", "<u4"), ("job", "<u4")])
+    ent["in_off"] = ent["out_off"] = offs
+    ent["segment_len"] = lens
+    xw = torch.randn(int(lens.sum()), dtype=torch.complex64, device="cuda")
+    yw = torch.empty_like(xw)
+    with fs.WorkList(ent) as wl:
+        te = _time(torch, lambda: wl.exec_ptr(xw.data_ptr(), yw.data_ptr(), sh), args.steps)
+        tgr = _time(torch, lambda: wl.exec_ptr(xw.data_ptr(), yw.data_ptr(), sh, graph=True),
+                    args.steps)
+    seqs["worklist_8_segments_per_length"] = {"us_per_exec": round(te * 1e6, 2),
+                                              "us_per_graph_exec": round(tgr * 1e6, 2)}
     print(json.dumps({"workload": workloads.SMALL["name"], "segment_len": n, "batch": b,
                       "us_per_exec": round(t * 1e6, 2), "us_per_graph_exec": round(tg * 1e6, 2),
                       "GFLOP/s": round(FLOP(n) * b / t / 1e9, 1),
-                      "GB/s": round(16 * n * b / t / 1e9, 1)}), flush=True)
+                      "GB/s": round(16 * n * b / t / 1e9, 1),
+                      "launch_sequences": seqs}), flush=True)
     return 0
 
 
@@ -218,7 +253,9 @@ def streamed(args):
     host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 4
     drain_threads = max(2, host_threads // 4)
     fill, drain, src, chk = sig.checked_chunk_source(seg, chunks, drain_threads=drain_threads)
-    rc, failed, stg = plan.exec_stream(chunks, (fill, src), (drain, src), 3)
+    # four slots: a chunk's slots come free only after its copy back and its
+    # drain, about two fills' time after its own fill
+    rc, failed, stg = plan.exec_stream(chunks, (fill, src), (drain, src), 4)
     tl_gen = plan.stream_timeline()
     plan.close()
     if rc != 0:
