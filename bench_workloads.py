@@ -249,10 +249,14 @@ def streamed(args):
     # (2) as configured: generated from the seed, every segment checked
     # the drain's sums are memory-bound: a quarter of the host threads keeps
     # up with the fill and leaves it the rest
+    # (the two run at once on different threads: the host's threads are split
+    # between them, so neither OpenMP team spins on cores the other needs)
     import os
     host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 4
-    drain_threads = max(2, host_threads // 4)
-    fill, drain, src, chk = sig.checked_chunk_source(seg, chunks, drain_threads=drain_threads)
+    drain_threads = max(1, host_threads // 4)
+    fill_threads = max(1, host_threads - drain_threads)
+    fill, drain, src, chk = sig.checked_chunk_source(seg, chunks, threads=fill_threads,
+                                                     drain_threads=drain_threads)
     # four slots: a chunk's slots come free only after its copy back and its
     # drain, about two fills' time after its own fill
     rc, failed, stg = plan.exec_stream(chunks, (fill, src), (drain, src), 4)
@@ -307,6 +311,7 @@ def streamed(args):
                "fill_s": round(stg["fill_s"], 3),
                "generation_GBps": round(stg["bytes_h2d"] / max(stg["fill_s"], 1e-9) / 1e9, 2),
                "drain_s": round(stg["drain_s"], 3),
+               "fill_threads": fill_threads,
                "drain_note": "per-segment output energies (Parseval) and the kept segments, "
                              "on %d threads, overlapping the fill" % drain_threads,
                "h2d_s": round(stg["h2d_s"], 3), "d2h_s": round(stg["d2h_s"], 3),

@@ -21,14 +21,14 @@ class routes:
     the work-list kernel's tiles, 1 + k = the k-th indexed one-pass kernel
     (grid: its own).  Cleared on exit."""
 
-    def __init__(self, table, tmp_path):
-        self.table, self.path = table, str(tmp_path / "routes.json")
+    def __init__(self, table, tmp_path, grid=0):
+        self.table, self.path, self.grid = table, str(tmp_path / "routes.json"), grid
 
     def __enter__(self):
         import json
         import torch
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-        ents = [{"n": n, "variant": -2, "grid_mult": 0, "wl_route": r, "wl_grid": 0}
+        ents = [{"n": n, "variant": -2, "grid_mult": 0, "wl_route": r, "wl_grid": self.grid}
                 for n, r in self.table.items()]
         json.dump({"arch": arch, "entries": ents}, open(self.path, "w"))
         assert fs.tune_load(self.path) == len(ents)
@@ -319,6 +319,37 @@ def test_uneven_workload_full_size():
             assert e <= oracle.tolerance(n), (n, i, e)
             worst = max(worst, e / oracle.tolerance(n))
     print("  sampled 16 per length, worst error / bound %.3f" % worst, flush=True)
+
+
+@pytest.mark.parametrize("route", [1, 2])
+def test_indexed_routes_walk_several_segments(route, tmp_path):
+    """The indexed one-pass launches on a grid of one resident wave of
+    workgroups (wl_grid 1), over enough segments of each length that every
+    workgroup transforms several tiles in turn; the 65536-point segments
+    through the indexed passes at the same grid.  Sampled segments of every
+    length (the first, the last and 40 drawn) against the oracle."""
+    import torch
+    counts = {256: 40000, 1000: 12000, 1536: 8000, 4096: 3000, 6000: 2000, 65536: 20}
+    rng = np.random.default_rng(40 + route)
+    lengths = np.concatenate([np.full(c, n, np.int64) for n, c in counts.items()])
+    rng.shuffle(lengths)
+    in_off, total = packed(lengths, gap=1)
+    announce("indexed routes=%d on one resident wave, %d segments" % (route, len(lengths)))
+    x = siggen.Signal(seed=41, seg_len=1, sigma=1.0).samples(0, total)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros(total, dtype=torch.complex64, device="cuda")
+    table = {n: (route if n != 65536 else 1) for n in counts}
+    with routes(table, tmp_path, grid=1), fs.WorkList(to_entries(in_off, in_off, lengths)) as wl:
+        d = wl.describe()
+        assert d["indexed_two_pass_segments"] == counts[65536]
+        wl.exec(xd, yd)
+        wl.status()
+    y = yd.cpu().numpy()
+    sample = []
+    for n in counts:
+        idx = np.nonzero(lengths == n)[0]
+        sample += [int(idx[0]), int(idx[-1])] + [int(i) for i in rng.choice(idx, 40)]
+    check_all(x, y, in_off, in_off, lengths, sample=sample)
 
 
 @pytest.mark.parametrize("route", [0, 1, 2])
