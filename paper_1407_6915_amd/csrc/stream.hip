@@ -271,39 +271,66 @@ extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn f
             std::string msg;
         } sh;
         std::thread worker([&] {
-            for (uint64_t c = 0;; ++c) {
-                {
-                    std::unique_lock<std::mutex> lk(sh.mu);
-                    sh.cv.wait(lk, [&] { return c < sh.issued || sh.done_issuing; });
-                    if (c >= sh.issued)
+            uint64_t c = 0;
+            try {
+                for (;; ++c) {
+                    {
+                        std::unique_lock<std::mutex> lk(sh.mu);
+                        sh.cv.wait(lk, [&] { return c < sh.issued || sh.done_issuing; });
+                        if (c >= sh.issued)
+                            return;
+                    }
+                    int s2 = pl.wait_chunk(c, stats);
+                    if (s2 == FFT_OK && drain) {
+                        const double t0 = now_s();
+                        const int rc = drain(user, c, S->ring.out[c % n_slots], bytes);
+                        if (stats)
+                            stats->drain_s += now_s() - t0;
+                        if (rc != 0)
+                            s2 = set_error(FFT_ERR_CALLBACK,
+                                           "drain callback returned %d at chunk %llu", rc,
+                                           (unsigned long long)c);
+                    }
+                    std::lock_guard<std::mutex> lk(sh.mu);
+                    if (s2 != FFT_OK) {
+                        // status and message are thread-local: carry them over
+                        sh.failed = true;
+                        sh.fail_at = c;
+                        sh.code = last_status();
+                        sh.msg = last_message();
+                        sh.cv.notify_all();
                         return;
-                }
-                int s2 = pl.wait_chunk(c, stats);
-                if (s2 == FFT_OK && drain) {
-                    const double t0 = now_s();
-                    const int rc = drain(user, c, S->ring.out[c % n_slots], bytes);
+                    }
+                    sh.drained = c + 1;
                     if (stats)
-                        stats->drain_s += now_s() - t0;
-                    if (rc != 0)
-                        s2 = set_error(FFT_ERR_CALLBACK, "drain callback returned %d at chunk %llu",
-                                       rc, (unsigned long long)c);
-                }
-                std::lock_guard<std::mutex> lk(sh.mu);
-                if (s2 != FFT_OK) {
-                    // status and message are thread-local: carry them over
-                    sh.failed = true;
-                    sh.fail_at = c;
-                    sh.code = last_status();
-                    sh.msg = last_message();
+                        stats->chunks_done = c + 1;
                     sh.cv.notify_all();
-                    return;
                 }
-                sh.drained = c + 1;
-                if (stats)
-                    stats->chunks_done = c + 1;
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(sh.mu);
+                sh.failed = true;
+                sh.fail_at = c;
+                sh.code = FFT_ERR_OUT_OF_MEMORY;
+                sh.msg = "host allocation failed";
                 sh.cv.notify_all();
             }
         });
+        // whatever way this function leaves, the worker is told that no
+        // more chunks come and is joined first
+        struct Joiner {
+            std::thread &t;
+            Shared &sh;
+            ~Joiner()
+            {
+                {
+                    std::lock_guard<std::mutex> lk(sh.mu);
+                    sh.done_issuing = true;
+                    sh.cv.notify_all();
+                }
+                if (t.joinable())
+                    t.join();
+            }
+        } joiner{worker, sh};
         int fail = FFT_OK;
         uint64_t fail_at = UINT64_MAX;
         std::string fail_msg;
@@ -350,7 +377,7 @@ extern "C" int fft_exec_stream(fft_plan_t plan, uint64_t n_chunks, fft_fill_fn f
             sh.done_issuing = true;
             sh.cv.notify_all();
         }
-        worker.join();
+        worker.join();  // (the joiner then finds it joined)
         (void)hipStreamSynchronize(pl.s_in);
         (void)hipStreamSynchronize(pl.s_comp);
         (void)hipStreamSynchronize(pl.s_out);
