@@ -492,14 +492,6 @@ int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant
         // (one line more: Y may start at the input's offset within a line)
         p->sub_batch = std::min<uint64_t>(batch, max_sub_samples / n);
         p->scratch_bytes = (p->sub_batch * n + kLineSamples) * sizeof(c32);
-        if (const char *e = getenv("FFTSEG_FOURSTEP_PIPE")) {
-            const uint64_t segs = strtoull(e, nullptr, 10);
-            if (segs > 0 && segs < batch) {
-                p->pipe = segs;
-                p->sub_batch = segs;
-                p->scratch_bytes = (2 * segs * n + kLineSamples) * sizeof(c32);
-            }
-        }
     } else {
         p->kind = Plan::GENERIC;
         p->radices = generic_radices(n);
@@ -630,20 +622,6 @@ void plan_free(Plan *p)
         (void)hipGraphDestroy(p->graph);
     if (p->capture_stream)
         (void)hipStreamDestroy(p->capture_stream);
-    for (int i = 0; i < 2; ++i) {
-        if (p->pipe_s[i]) {
-            (void)hipStreamSynchronize(p->pipe_s[i]);
-            (void)hipStreamDestroy(p->pipe_s[i]);
-        }
-        for (hipEvent_t e : {p->pipe_a[i], p->pipe_b[i], p->pipe_join[i]})
-            if (e)
-                (void)hipEventDestroy(e);
-        p->pipe_s[i] = nullptr;
-        p->pipe_a[i] = p->pipe_b[i] = p->pipe_join[i] = nullptr;
-    }
-    if (p->pipe_fork)
-        (void)hipEventDestroy(p->pipe_fork);
-    p->pipe_fork = nullptr;
     p->graph_exec = nullptr;
     p->graph = nullptr;
     p->capture_stream = nullptr;
@@ -746,62 +724,6 @@ int identity_copy(const void *in, void *out, uint64_t n, hipStream_t s)
 }
 
 // enqueue the transform of `batch` segments (arguments already checked)
-// Four-step over sub-batches on two side streams: pass A of sub-batch k
-// (stream 0) writes Y buffer k % 2, pass B of sub-batch k (stream 1) waits
-// for it and reads it, and pass A of sub-batch k + 2 waits for that pass B
-// before it overwrites the buffer.  Pass A of the next sub-batch thus runs
-// beside pass B of this one, and with small sub-batches Y can stay in the
-// memory-side cache between its two passes.  Forked from and joined back
-// into the caller's stream through events.
-int four_step_pipelined(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s)
-{
-    hipError_t e;
-    for (int i = 0; i < 2; ++i) {
-        if (!p->pipe_s[i] &&
-            (e = hipStreamCreateWithFlags(&p->pipe_s[i], hipStreamNonBlocking)) != hipSuccess)
-            return hip_error(e, "hipStreamCreate");
-        for (hipEvent_t *q : {&p->pipe_a[i], &p->pipe_b[i], &p->pipe_join[i]})
-            if (!*q && (e = hipEventCreateWithFlags(q, hipEventDisableTiming)) != hipSuccess)
-                return hip_error(e, "hipEventCreate");
-    }
-    if (!p->pipe_fork &&
-        (e = hipEventCreateWithFlags(&p->pipe_fork, hipEventDisableTiming)) != hipSuccess)
-        return hip_error(e, "hipEventCreate");
-    const uint64_t n = p->n;
-    const ColumnDesc *cd = p->col;
-    const RowDesc *rd = p->row;
-    hipStream_t sa = p->pipe_s[0], sb = p->pipe_s[1];
-    (void)hipEventRecord(p->pipe_fork, s);
-    (void)hipStreamWaitEvent(sa, p->pipe_fork, 0);
-    (void)hipStreamWaitEvent(sb, p->pipe_fork, 0);
-    const int dir = p->dir;
-    uint64_t k = 0;
-    for (uint64_t s0 = 0; s0 < batch; s0 += p->sub_batch, ++k) {
-        const uint64_t sb_n = std::min(p->sub_batch, batch - s0);
-        c32 *y = (c32 *)p->scratch + (k & 1) * p->sub_batch * n;
-        const uint64_t ta = sb_n * (p->n2 / (uint64_t)cd->cols);
-        const uint64_t tb = sb_n * (p->n1 / (uint64_t)rd->rows);
-        const unsigned ga = grid_for(cd->kernel[dir > 0], cd->threads * cd->cols, ta, p->device,
-                                     p->grid_mult);
-        const unsigned gb = grid_for(rd->kernel[dir > 0], rd->threads * rd->rows, tb, p->device,
-                                     p->grid_mult);
-        if (k >= 2)
-            (void)hipStreamWaitEvent(sa, p->pipe_b[k & 1], 0);
-        cd->launch(dir, (const c32 *)in + s0 * n, y, p->tw, p->tl, p->th, p->sh, (int)p->n2,
-                   sb_n, ga, sa);
-        (void)hipEventRecord(p->pipe_a[k & 1], sa);
-        (void)hipStreamWaitEvent(sb, p->pipe_a[k & 1], 0);
-        rd->launch(dir, y, (c32 *)out + s0 * n, p->tw2, (int)p->n1, sb_n, gb, sb);
-        (void)hipEventRecord(p->pipe_b[k & 1], sb);
-    }
-    (void)hipEventRecord(p->pipe_join[0], sa);
-    (void)hipEventRecord(p->pipe_join[1], sb);
-    (void)hipStreamWaitEvent(s, p->pipe_join[0], 0);
-    (void)hipStreamWaitEvent(s, p->pipe_join[1], 0);
-    e = hipGetLastError();
-    return e == hipSuccess ? FFT_OK : hip_error(e, "pipelined four-step launch");
-}
-
 int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t s)
 {
     const uint64_t n = p->n;
@@ -871,12 +793,6 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
     case Plan::FOURSTEP: {
         const ColumnDesc *cd = p->col;
         const RowDesc *rd = p->row;
-        if (p->pipe && batch > p->pipe) {
-            int st = four_step_pipelined(p, in, out, batch, s);
-            if (st != FFT_OK)
-                return st;
-            break;
-        }
         // Segments that start inside a 128-byte line (a base pointer off a
         // line boundary): column blocks start at the first line-aligned
         // column and wrap round, Y sits at the input's offset within a

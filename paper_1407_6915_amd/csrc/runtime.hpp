@@ -46,13 +46,6 @@ struct Plan {
     // buffer of its spectra (forward) or inputs (inverse), sub_batch rows
     Plan *inner = nullptr;
     void *zbuf = nullptr;
-    // FOURSTEP with pipe > 0: sub-batches of `pipe` segments, pass A of
-    // sub-batch k + 1 on one side stream while pass B of sub-batch k runs
-    // on another, Y double-buffered (the scratch holds two sub-batches)
-    uint64_t pipe = 0;
-    hipStream_t pipe_s[2] = {nullptr, nullptr};
-    hipEvent_t pipe_a[2] = {nullptr, nullptr}, pipe_b[2] = {nullptr, nullptr};
-    hipEvent_t pipe_fork = nullptr, pipe_join[2] = {nullptr, nullptr};
 };
 
 inline bool is_real(const Plan *p) { return p->kind == Plan::REAL || p->kind == Plan::REAL_SPLIT; }
