@@ -16,10 +16,12 @@ namespace fs {
 // overlapping, windowed frames; both passes also come in a form whose blocks
 // start at any column / row and wrap round (for segments off a line
 // boundary); both passes also come in a form over segments at listed
-// offsets (kIndexed); one row per length carries each of these forms
+// offsets (kIndexed); one row per length carries each of these forms;
+// the column pass splits W_N^{n2 k1} into a per-butterfly lookup and a
+// per-tile LDS table (kLdsTw, ColumnPolicy)
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
               kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048,
-              kIndexed = 4096;
+              kIndexed = 4096, kLdsTw = 8192;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -43,10 +45,10 @@ struct ColInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
     using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                              (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                             (F & kSplit) != 0>;
+                             (F & kSplit) != 0, false, (F & kLdsTw) != 0>;
     using PolW = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                               (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                              (F & kSplit) != 0, true>;
+                              (F & kSplit) != 0, true, (F & kLdsTw) != 0>;
     static void launch_shifted(int dir, const void *in, void *ybuf, const void *tw,
                                const void *tl, const void *th, int sh, int n2, uint64_t batch,
                                int shift, unsigned grid, hipStream_t s)

@@ -7,13 +7,17 @@ namespace {
 
 using namespace fs;
 
-// Variant 0 of each length is the default; the tuner tries the others.
+// Variant 0 of each length is the default; the tuner tries the others.  The
+// default column tiles split W_N^{n2 k1} through LDS (kLdsTw); the last
+// column variant of each length is the default tile with two table reads
+// per output instead.
 //                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
-    ColInst<128, 8, 16, 4, kFrames | kShifted, 16, 8>::desc(0),
+    ColInst<128, 8, 16, 4, kFrames | kShifted | kLdsTw, 16, 8>::desc(0),
     ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     ColInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames | kShifted, 16, 16>::desc(0),
+    ColInst<128, 8, 16, 4, 0, 16, 8>::desc(3),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames | kShifted | kLdsTw, 16, 16>::desc(0),
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
@@ -21,11 +25,13 @@ const ColumnDesc kColumns[] = {
     ColInst<256, 16, 16, 4, kXcd | kPlainLane, 16, 16>::desc(5),
     ColInst<256, 16, 16, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(6),
     ColInst<256, 16, 32, 4, kNT | kXcd | kPlainLane, 16, 16>::desc(7),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast, 16, 16>::desc(8),
     radix32_column_desc(1, 0),
     ColInst<512, 64, 8, 4, 0, 8, 8, 8>::desc(1),
     ColInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(2),
     ColInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(3),
     radix32_column_desc(2, 4),
+    radix32_column_desc(4, 5),
     radix32_column_desc(0, 0),
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
@@ -39,10 +45,13 @@ const ColumnDesc kColumns[] = {
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(10),
     split_column_desc(0, 11),
     split_column_desc(2, 12),
-    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames | kShifted, 16, 16, 8>::desc(0),
+    radix32_column_desc(3, 13),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames | kShifted | kLdsTw, 16, 16,
+            8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(1),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(2),
     split_column_desc(1, 3),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(4),
 };
 
 const RowDesc kRows[] = {

@@ -45,8 +45,8 @@ const SinglePassDesc kIdx16384[] = {
 
 // the 65536-point two-pass tiles (256 x 256), as the plan's defaults
 const ColumnDesc kIdxCol65536 =
-    fs::ColInst<256, 16, 16, 4, fs::kNT | fs::kXcd | fs::kHoistLast | fs::kIndexed, 16,
-                16>::desc(0);
+    fs::ColInst<256, 16, 16, 4, fs::kNT | fs::kXcd | fs::kHoistLast | fs::kIndexed | fs::kLdsTw,
+                16, 16>::desc(0);
 const RowDesc kIdxRow65536 =
     fs::RowInst<256, 16, 16, 4, fs::kNT | fs::kXcd | fs::kHoistLast | fs::kIndexed, 16,
                 16>::desc(0);

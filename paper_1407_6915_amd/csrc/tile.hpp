@@ -919,18 +919,31 @@ struct FourStepCtx {
     const c32 *__restrict__ th;
     int sh;
     bool valid;
+    // pass A with the twiddle factors split in LDS: W_N^{n2 r NB} for the
+    // tile's columns and the last stage's outputs r (column-fastest)
+    const c32 *ltw = nullptr;
 };
 
 // Pass A: lanes column-fastest (c = tid % C, t = tid / C) in every stage.
+//
+// LdsTw: the factor W_N^{n2 k1} of output k1 = b + r NB of the last stage
+// (NB butterflies of radix R) is formed as W_N^{n2 b} W_N^{n2 r NB}.  The
+// first is one table lookup per butterfly b a thread owns; the second,
+// shared by every thread of a column, is looked up once per tile into LDS
+// (R x C values, two buffers alternating between consecutive tiles), so an
+// output costs one LDS read instead of two table reads.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
-          bool Wrap_ = false>
+          bool Wrap_ = false, bool LdsTw_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     // Wrap: tile columns are first + c modulo the (power-of-two) column
     // count, so blocks may start at any column and the last one wraps
     static constexpr bool kWrap = Wrap_;
+    static constexpr bool kLdsTw = LdsTw_;
+    static_assert(!(kLdsTw && kSplit), "LDS twiddles need the complex exchange layout");
+    static_assert(!kLdsTw || Sh::NS > 1, "the LDS twiddles are ordered by the exchange barriers");
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
     static constexpr bool kPlainLane = PlainLane_;  // as in SinglePassPolicy
@@ -940,7 +953,11 @@ struct ColumnPolicy {
     static constexpr int kWaves = Waves_;
     static constexpr bool hoists(int stage) { return (kHoistMask >> stage) & 1; }
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
-    static constexpr int kLdsElems = (pad(Sh::M - 1) + 1) * C;
+    static constexpr int kLastR = Sh::Rad::at(Sh::NS - 1);
+    static constexpr int kLastNB = Sh::M / kLastR;
+    static constexpr int kExchElems = (pad(Sh::M - 1) + 1) * C;
+    static constexpr int kTwElems = kLdsTw ? kLastR * C : 0;
+    static constexpr int kLdsElems = kExchElems + 2 * kTwElems;
     static constexpr int kThreads = Sh::T * C;
     using Ctx = FourStepCtx;
     template <int I>
@@ -964,6 +981,25 @@ struct ColumnPolicy {
         const unsigned n2 = kWrap ? (unsigned)((ctx.first + c) & (ctx.n2 - 1))
                                   : (unsigned)(ctx.first + c);
         const unsigned mask = (1u << ctx.sh) - 1u;
+        if constexpr (kLdsTw) {
+            static_assert(St::R == kLastR, "the store sees the last stage");
+            const c32 *bw = ctx.ltw + c;
+#pragma unroll
+            for (int u = 0; u < St::U; ++u) {
+                const int b = t + u * Sh::T;
+                if (St::kFull || b < St::NB) {
+                    const unsigned m = n2 * (unsigned)b;
+                    const c32 a = cmul(ctx.th[m >> ctx.sh], ctx.tl[m & mask]);
+#pragma unroll
+                    for (int r = 0; r < St::R; ++r) {
+                        const unsigned k1 = (unsigned)(b + r * St::NB);
+                        gstore<kNT>(ctx.y + (size_t)k1 * ctx.n2 + n2,
+                                    twiddle<D>(v[u * St::R + r], cmul(a, bw[r * C])));
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < St::U; ++u) {
             const int b = t + u * Sh::T;
@@ -981,15 +1017,41 @@ struct ColumnPolicy {
     }
 };
 
+// Pol::kLdsTw: the tile's W_N^{n2 r NB} into the LDS buffer of parity
+// `par` (consecutive tiles of a workgroup alternate).  Written before the
+// tile's first exchange barrier and read after it; a workgroup reaches the
+// next tile's write to the same buffer only after the barriers of the tile
+// between, which every thread enters after its store.
+template <class Sh, class Pol>
+__device__ __forceinline__ void column_lds_twiddles(c32 *lds, FourStepCtx &ctx, int par,
+                                                    int tid)
+{
+    if constexpr (Pol::kLdsTw) {
+        c32 *ltw = lds + Pol::kExchElems + (par & 1) * Pol::kTwElems;
+        const unsigned mask = (1u << ctx.sh) - 1u;
+        for (int e = tid; e < Pol::kTwElems; e += Pol::kThreads) {
+            const int r = e / Pol::C, c = e - (e / Pol::C) * Pol::C;
+            const unsigned n2 = Pol::kWrap ? (unsigned)((ctx.first + c) & (ctx.n2 - 1))
+                                           : (unsigned)(ctx.first + c);
+            const unsigned m = n2 * (unsigned)(r * Pol::kLastNB);  // < N1 N2
+            ltw[e] = cmul(ctx.th[m >> ctx.sh], ctx.tl[m & mask]);
+        }
+        ctx.ltw = ltw;
+    }
+}
+
 // One pass-A tile: columns first..first+C-1 of one segment (x: segment
-// input, y: the segment's Y buffer, n2 columns).
+// input, y: the segment's Y buffer, n2 columns); par: the tile's parity in
+// the workgroup's sequence (LDS twiddle buffer).
 template <class Sh, class Pol, int D>
 __device__ __forceinline__ void column_tile(c32 *lds, const c32 *__restrict__ tw,
                                             const c32 *__restrict__ tl,
                                             const c32 *__restrict__ th, int sh, int tid,
-                                            int tid_tw, const c32 *x, c32 *y, int first, int n2)
+                                            int tid_tw, const c32 *x, c32 *y, int first, int n2,
+                                            int par)
 {
     FourStepCtx ctx{x, y, first, Sh::M, n2, tl, th, sh, true};
+    column_lds_twiddles<Sh, Pol>(lds, ctx, par, tid);
     const int c = Pol::template col<0>(tid);
     const int t = Pol::template thr<0>(tid);
     c32 v[Sh::kMaxE];
@@ -1013,7 +1075,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+    int par = 0;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x, par ^= 1) {
         const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
         if (g >= tiles)
             continue;
@@ -1021,7 +1084,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         const int first = (int)(g - seg * blocks) * Pol::C;
         column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
                                 Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
-                                in + seg * nseg, ybuf + seg * nseg, first, n2);
+                                in + seg * nseg, ybuf + seg * nseg, first, n2, par);
     }
 }
 
@@ -1041,7 +1104,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+    int par = 0;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x, par ^= 1) {
         const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
         if (g >= tiles)
             continue;
@@ -1049,7 +1113,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         const int first = (int)(g - seg * blocks) * Pol::C + shift;
         column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
                                 Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
-                                in + seg * nseg, ybuf + seg * nseg, first, n2);
+                                in + seg * nseg, ybuf + seg * nseg, first, n2, par);
     }
 }
 
@@ -1069,7 +1133,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+    int par = 0;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x, par ^= 1) {
         const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
         if (g >= tiles)
             continue;
@@ -1078,7 +1143,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         const int tid = Pol::kPlainLane ? (int)threadIdx.x : opaque_lane();
         const int c = Pol::template col<0>(tid);
         const int t = Pol::template thr<0>(tid);
-        const FourStepCtx ctx{nullptr, ybuf + seg * nseg, first, Sh::M, n2, tl, th, sh, true};
+        FourStepCtx ctx{nullptr, ybuf + seg * nseg, first, Sh::M, n2, tl, th, sh, true};
+        column_lds_twiddles<Sh, Pol>(lds, ctx, par, tid);
         c32 v[Sh::kMaxE];
         const c32 *xc = in + seg * hop + first + c;
         if (window) {
@@ -1250,7 +1316,8 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
     const uint64_t nseg = (uint64_t)Sh::M * (uint64_t)n2;
     const uint64_t blocks = (uint64_t)(n2 / Pol::C);
     const uint64_t tiles = batch * blocks;
-    for (uint64_t base = 0; base < tiles; base += gridDim.x) {
+    int par = 0;
+    for (uint64_t base = 0; base < tiles; base += gridDim.x, par ^= 1) {
         const uint64_t g = tile_of<Pol::kXcd>(base, blockIdx.x, gridDim.x);
         if (g >= tiles)
             continue;
@@ -1260,7 +1327,7 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         const int first = (int)(g - seg * blocks) * Pol::C + ((kIdxLine - in_m) & (kIdxLine - 1));
         column_tile<Sh, Pol, D>(lds, tw, tl, th, sh,
                                 Pol::kPlainLane ? (int)threadIdx.x : opaque_lane(), threadIdx.x,
-                                x, ybuf + seg * (nseg + kIdxLine) + in_m, first, n2);
+                                x, ybuf + seg * (nseg + kIdxLine) + in_m, first, n2, par);
     }
 }
 

@@ -156,11 +156,13 @@ __device__ __forceinline__ void run_columns(c32 *lds, const Tables &tb, const Ta
                                             const Item *__restrict__ items, const c32 *in,
                                             c32 *ybuf, int tid0, int n2)
 {
+    static_assert(!Pol::kLdsTw, "work-list tiles take their twiddles from the tables");
     const Item it = items[t.item];
     for (uint32_t k = 0; k < t.ntiles; ++k) {
         const int tid = opaque(tid0);
         column_tile<Sh, Pol, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, tid, in + it.in_off,
-                                ybuf + it.y_off, (int)((t.tile + k) * Pol::C + t.shift), n2);
+                                ybuf + it.y_off, (int)((t.tile + k) * Pol::C + t.shift), n2,
+                                0);
     }
 }
 

@@ -93,16 +93,19 @@ def test_every_variant_walks_several_segments(n, monkeypatch):
             assert np.all(e <= oracle.tolerance(n)), (v, d, float(e.max()))
 
 
-def test_four_step_tiles_walk_several_tiles(monkeypatch):
-    """The same for the column and row passes of the 2^20-point split."""
+@pytest.mark.parametrize("n,b", [(1 << 15, 400), (1 << 16, 200), (1 << 18, 40), (1 << 20, 9),
+                                 (1 << 22, 3)])
+def test_four_step_tiles_walk_several_tiles(monkeypatch, n, b):
+    """The same for the column and row passes of two-pass splits: every
+    column and every row tile variant, at batches that give each resident
+    workgroup two or more tiles (tiles alternate LDS twiddle buffers)."""
     import torch
     monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
-    n, b = 1 << 20, 9
     n1, n2, nc, nr = fs.split_info(n)
     x = noise(n, b, seed=29)
     ref = {d: oracle.fft_recursive(x, n, d) for d in (fs.FORWARD, fs.INVERSE)}
     xd = torch.from_numpy(x.reshape(-1)).cuda()
-    for c, r in [(0, 0)] + [(v, v) for v in range(1, min(nc, nr))]:
+    for c, r in [(min(v, nc - 1), min(v, nr - 1)) for v in range(max(nc, nr))]:
         announce("n=%d column variant %d row variant %d batch=%d grid_mult=1" % (n, c, r, b))
         for d in (fs.FORWARD, fs.INVERSE):
             with fs.Plan(n, b, d, split_variants=(c, r)) as p:
