@@ -96,7 +96,7 @@ using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
 // segments alone are about 5 % slower under the tighter register budget)
 using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false, 1, false, false, false, true>;
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
-using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
+using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true, true>;
 using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -156,13 +156,15 @@ __device__ __forceinline__ void run_columns(c32 *lds, const Tables &tb, const Ta
                                             const Item *__restrict__ items, const c32 *in,
                                             c32 *ybuf, int tid0, int n2)
 {
-    static_assert(!Pol::kLdsTw, "work-list tiles take their twiddles from the tables");
+    // LDS twiddle buffers alternate over the task's tiles; the barrier that
+    // ends every task orders the next task's first write after this one's
+    // last reads
     const Item it = items[t.item];
     for (uint32_t k = 0; k < t.ntiles; ++k) {
         const int tid = opaque(tid0);
         column_tile<Sh, Pol, D>(lds, tb.tw, tb.tl, tb.th, tb.sh, tid, tid, in + it.in_off,
                                 ybuf + it.y_off, (int)((t.tile + k) * Pol::C + t.shift), n2,
-                                0);
+                                (int)(k & 1));
     }
 }
 
