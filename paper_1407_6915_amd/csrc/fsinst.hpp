@@ -18,10 +18,11 @@ namespace fs {
 // boundary); both passes also come in a form over segments at listed
 // offsets (kIndexed); one row per length carries each of these forms;
 // the column pass splits W_N^{n2 k1} into a per-butterfly lookup and a
-// per-tile LDS table (kLdsTw, ColumnPolicy)
+// per-tile LDS table (kLdsTw, ColumnPolicy); stages that reload their
+// twiddles read them as pairs (kTwPair, tw_pair_low)
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
               kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048,
-              kIndexed = 4096, kLdsTw = 8192;
+              kIndexed = 4096, kLdsTw = 8192, kTwPair = 16384;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -45,10 +46,12 @@ struct ColInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
     using Pol = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                              (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                             (F & kSplit) != 0, false, (F & kLdsTw) != 0>;
+                             (F & kSplit) != 0, false, (F & kLdsTw) != 0,
+                             (F & kTwPair) != 0>;
     using PolW = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                               (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                              (F & kSplit) != 0, true, (F & kLdsTw) != 0>;
+                              (F & kSplit) != 0, true, (F & kLdsTw) != 0,
+                              (F & kTwPair) != 0>;
     static void launch_shifted(int dir, const void *in, void *ybuf, const void *tw,
                                const void *tl, const void *th, int sh, int n2, uint64_t batch,
                                int shift, unsigned grid, hipStream_t s)
@@ -146,10 +149,10 @@ struct RowInst {
     using Sh = Shape<M, T, Radices<Rs...>>;
     using Pol = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                           (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                          (F & kSplit) != 0>;
+                          (F & kSplit) != 0, false, (F & kTwPair) != 0>;
     using PolW = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                            (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
-                           (F & kSplit) != 0, true>;
+                           (F & kSplit) != 0, true, (F & kTwPair) != 0>;
     static void launch_shifted(int dir, const void *ybuf, void *out, const void *tw, int n1,
                                uint64_t batch, int shift, unsigned grid, hipStream_t s)
     {

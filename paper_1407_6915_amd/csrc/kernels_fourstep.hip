@@ -8,9 +8,9 @@ namespace {
 using namespace fs;
 
 // Variant 0 of each length is the default; the tuner tries the others.  The
-// default column tiles split W_N^{n2 k1} through LDS (kLdsTw); the last
-// column variant of each length is the default tile with two table reads
-// per output instead.
+// default column tiles split W_N^{n2 k1} through LDS (kLdsTw), and the 512-
+// and 1024-point tiles (kernels_radix32.hip) also read their second stage's
+// twiddles in pairs (kTwPair); the forms without these stay as variants.
 //                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
     ColInst<128, 8, 16, 4, kFrames | kShifted | kLdsTw, 16, 8>::desc(0),
@@ -32,6 +32,7 @@ const ColumnDesc kColumns[] = {
     ColInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(3),
     radix32_column_desc(2, 4),
     radix32_column_desc(4, 5),
+    radix32_column_desc(6, 6),
     radix32_column_desc(0, 0),
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
@@ -46,12 +47,14 @@ const ColumnDesc kColumns[] = {
     split_column_desc(0, 11),
     split_column_desc(2, 12),
     radix32_column_desc(3, 13),
+    radix32_column_desc(5, 14),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames | kShifted | kLdsTw, 16, 16,
             8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(1),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(2),
     split_column_desc(1, 3),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(4),
+    ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kLdsTw | kTwPair, 16, 16, 8>::desc(5),
 };
 
 const RowDesc kRows[] = {
@@ -71,6 +74,7 @@ const RowDesc kRows[] = {
     RowInst<512, 64, 8, 4, kXcd, 8, 8, 8>::desc(2),
     RowInst<512, 64, 8, 4, kXcd | kPlainLane, 8, 8, 8>::desc(3),
     radix32_row_desc(2, 4),
+    radix32_row_desc(4, 5),
     radix32_row_desc(0, 0),
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
@@ -84,10 +88,12 @@ const RowDesc kRows[] = {
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 4>::desc(10),
     split_row_desc(0, 11),
     split_row_desc(2, 12),
+    radix32_row_desc(3, 13),
     RowInst<2048, 128, 8, 4, kNoHoist | kShifted, 16, 16, 8>::desc(0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),
     split_row_desc(1, 3),
+    RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kTwPair, 16, 16, 8>::desc(4),
 };
 
 template <int R>

@@ -1,8 +1,10 @@
 // Four-step tiles with radix-32 stages: 1024 = 32 x 32 and 512 = 32 x 16
 // take two Stockham stages, so one LDS exchange (two barriers) per tile
-// instead of two or three, for 32 values per thread.  The default column
-// tiles (config 0 and 1) split W_N^{n2 k1} through LDS (kLdsTw); configs 3
-// and 4 are the same tiles with two table reads per output.  (The same radices in
+// instead of two or three, for 32 values per thread.  The default tiles
+// (configs 0 and 1) read the second stage's twiddles in pairs (kTwPair),
+// and the column tiles split W_N^{n2 k1} through LDS (kLdsTw); the column
+// configs 3 / 4 are those tiles with neither, 5 / 6 without the pairs, and
+// the row configs 3 / 4 without the pairs.  (The same radices in
 // one-pass kernels of 512 and 1024 points measured no faster than the
 // table's defaults.)  Kept in a translation unit of their own so they do not
 // share inlined code with the other instances.
@@ -16,10 +18,12 @@ ColumnDesc radix32_column_desc(int config, int variant)
     //                        M     T   C  PS  F                        radices
     switch (config) {
     case 0:
-        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw, 32,
+        return ColInst<1024, 32, 16, 4,
+                       kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
                        32>::desc(variant);
     case 1:
-        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw, 32,
+        return ColInst<512, 16, 16, 4,
+                       kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
                        16>::desc(variant);
     case 2:
         return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
@@ -27,6 +31,10 @@ ColumnDesc radix32_column_desc(int config, int variant)
         return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
     case 4:
         return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
+    case 5:
+        return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kLdsTw, 32, 32>::desc(variant);
+    case 6:
+        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kLdsTw, 32, 16>::desc(variant);
     default:
         return ColumnDesc{};
     }
@@ -37,11 +45,17 @@ RowDesc radix32_row_desc(int config, int variant)
     using namespace fs;
     switch (config) {
     case 0:
-        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kShifted, 32, 32>::desc(variant);
+        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32, 32>::desc(
+            variant);
     case 1:
-        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kShifted, 32, 16>::desc(variant);
+        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32, 16>::desc(
+            variant);
     case 2:
         return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
+    case 3:
+        return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
+    case 4:
+        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
     default:
         return RowDesc{};
     }

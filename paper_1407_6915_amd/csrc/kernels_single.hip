@@ -64,6 +64,8 @@ const SinglePassDesc kTable[] = {
     SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(4, 32),
     SpInst<8192, 512, 1, 4, kPrefetch | kNT, 16, 16, 16, 2>::desc(5, 32),
     SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(6, 16),
+    SpInst<8192, 512, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 16, 16, 2>::desc(7, 32),
+    split_desc(6, 8, 32),
     split_desc(0, 0, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(1, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),
@@ -72,6 +74,7 @@ const SinglePassDesc kTable[] = {
     split_desc(2, 5, 32),
     split_desc(3, 6, 32),
     split_desc(4, 7, 32),
+    split_desc(5, 8, 32),
     // mixed radix 2/3/5
     SpInst<1000, 100, 2, 4, kClassic, 10, 10, 10>::desc(0, 64),
     SpInst<1000, 100, 2, 4, kPlain, 10, 10, 10>::desc(1, 64),
@@ -81,7 +84,10 @@ const SinglePassDesc kTable[] = {
     SpInst<1536, 96, 2, 4, kPlain, 16, 16, 6>::desc(1, 32),
     SpInst<1536, 96, 2, 4, kNT, 16, 16, 6>::desc(2, 32),
     SpInst<1536, 96, 2, 4, kClassic | kNT, 16, 16, 6>::desc(3, 64),
-    SpInst<6000, 400, 1, 4, kClassic | kNT, 16, 15, 25>::desc(0, 32),
+    // twiddles reloaded per segment and read in pairs, registers for two
+    // workgroups per CU (79 VGPRs, three workgroups fit the LDS): 4.8-4.9
+    // TB/s against 4.1-4.2 for the plainly written kernel (variant 7)
+    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 15, 25>::desc(0, 32),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(1, 0),
     SpInst<6000, 300, 1, 4, kNT | kNoHoist | kAux, 20, 20, 15>::desc(2, 32),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist | kPlain, 16, 15, 25>::desc(3, 32),
@@ -91,6 +97,8 @@ const SinglePassDesc kTable[] = {
     SpInst<6000, 400, 1, 4, kClassic, 16, 15, 25>::desc(5, 32),
     // radix 25 first: stage 0 reads at a stride of 240 samples, whole lines
     SpInst<6000, 400, 1, 4, kClassic | kNT, 25, 15, 16>::desc(6, 32),
+    SpInst<6000, 400, 1, 4, kClassic | kNT, 16, 15, 25>::desc(7, 32),
+    SpInst<6000, 300, 1, 4, kNT | kNoHoist | kTwPair | kW4, 20, 20, 15>::desc(8, 32),
 };
 
 }  // namespace

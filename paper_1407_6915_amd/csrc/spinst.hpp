@@ -21,10 +21,12 @@ namespace sp {
 // kernel with the next segment's loads issued ahead (implies the classic
 // policy); kSplit = the kernel with split (real, then imaginary) LDS
 // exchanges; kW4 / kW8 = 4 / 8 waves per SIMD; kIndexed = the row also
-// provides the kernel over segments at listed offsets.
+// provides the kernel over segments at listed offsets; kTwPair = stages that
+// reload their twiddles read them as pairs (tw_pair_low).
 constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
               kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256,
-              kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096, kIndexed = 8192;
+              kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096, kIndexed = 8192,
+              kTwPair = 16384;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -43,7 +45,7 @@ struct SpInst {
     using Pol = SinglePassPolicy<Sh, S, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                                  false, waves<F>(), (F & kPlainLane) != 0,
                                  (F & kPlainLds) != 0, (F & (kClassic | kPrefetch)) != 0,
-                                 (F & kSplit) != 0>;
+                                 (F & kSplit) != 0, (F & kTwPair) != 0>;
     static_assert(!((F & kSplit) && (F & (kAux | kClassic))),
                   "split exchanges: transform kernels only");
 

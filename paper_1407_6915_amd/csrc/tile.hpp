@@ -116,15 +116,48 @@ __device__ __forceinline__ void st_gather(c32 *v, int t, Get &&get)
 // (Hoist = false keeps the twiddle loads inside a persistent loop: the
 // index is made opaque to the compiler so the loads are not lifted out and
 // held in registers across segments.)
-template <class St, class Sh, int L, int D, bool Hoist = true>
+// Paired twiddles: for a radix R = R1 R2 with R1 the smallest divisor whose
+// square reaches R (R >= 12), W^{(q R1 + j) e} = W^{q R1 e} W^{j e}, so a
+// butterfly reads R1 - 1 + R2 - 1 table entries instead of R - 1 and forms
+// the rest with one complex product each (0: direct reads).
+constexpr int tw_pair_low(int r)
+{
+    if (r < 12)
+        return 0;
+    for (int d = 2; d < r; ++d)
+        if (r % d == 0 && d * d >= r)
+            return d;
+    return 0;
+}
+
+template <class St, class Sh, int L, int D, bool Hoist = true, bool TwPair = false>
 __device__ __forceinline__ void st_compute(c32 *v, int t,
                                            const c32 *__restrict__ tw)
 {
+    constexpr int R1 = (TwPair && !Hoist) ? tw_pair_low(St::R) : 0;
 #pragma unroll
     for (int u = 0; u < St::U; ++u) {
         const int b = t + u * Sh::T;
         if (St::kFull || b < St::NB) {
-            if constexpr (L > 1) {
+            if constexpr (L > 1 && R1 > 0) {
+                int k = b % L;
+                asm volatile("" : "+v"(k));
+                c32 *x = v + u * St::R;
+                c32 wl[R1];
+#pragma unroll
+                for (int j = 1; j < R1; ++j) {
+                    wl[j] = tw[j * k * St::kTwStride];
+                    x[j] = twiddle<D>(x[j], wl[j]);
+                }
+#pragma unroll
+                for (int q = 1; q < St::R / R1; ++q) {
+                    const c32 wq = tw[q * R1 * k * St::kTwStride];
+                    x[q * R1] = twiddle<D>(x[q * R1], wq);
+#pragma unroll
+                    for (int j = 1; j < R1; ++j)
+                        x[q * R1 + j] = twiddle<D>(x[q * R1 + j], cmul(wq, wl[j]));
+                }
+            } else if constexpr (L > 1) {
                 int k = b % L;
                 if constexpr (!Hoist)
                     asm volatile("" : "+v"(k));
@@ -230,7 +263,8 @@ __device__ __forceinline__ void tile_run(c32 *v, c32 *lds,
     const int t = Pol::template thr<I>(tid);
     const bool act = Pol::active(tid);
     if (act)
-        st_compute<St, Sh, L, D, Pol::hoists(I)>(v, Pol::template thr<I>(tid_tw), tw);
+        st_compute<St, Sh, L, D, Pol::hoists(I), Pol::kTwPair>(v, Pol::template thr<I>(tid_tw),
+                                                              tw);
     if constexpr (St::kLast) {
         if (act)
             Pol::template store<St, D>(v, t, c, ctx);
@@ -355,7 +389,8 @@ __device__ __forceinline__ void tile_run_split(c32 *v, float *lds, const c32 *__
     const int t = Pol::template thr<I>(tid);
     const bool act = Pol::active(tid);
     if (act)
-        st_compute<St, Sh, L, D, Pol::hoists(I)>(v, Pol::template thr<I>(tid_tw), tw);
+        st_compute<St, Sh, L, D, Pol::hoists(I), Pol::kTwPair>(v, Pol::template thr<I>(tid_tw),
+                                                              tw);
     if constexpr (St::kLast) {
         if (act)
             Pol::template store<St, D>(v, t, c, ctx);
@@ -402,10 +437,14 @@ __device__ __forceinline__ int opaque_lane()
 // the waves per SIMD the register allocation must allow.)
 template <class Sh, int S_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Partial_ = false, int Waves_ = 1, bool PlainLane_ = false,
-          bool PlainLds_ = false, bool Classic_ = false, bool Split_ = false>
+          bool PlainLds_ = false, bool Classic_ = false, bool Split_ = false,
+          bool TwPair_ = false>
 struct SinglePassPolicy {
     static constexpr int S = S_;
     static constexpr int PS = PS_;
+    // TwPair: stages that reload their twiddles per segment read them as
+    // pairs (tw_pair_low)
+    static constexpr bool kTwPair = TwPair_;
     // PlainLane: the persistent loop keeps the lane index (and what the
     // compiler derives from it) across segments instead of recomputing it;
     // PlainLds: every LDS access computes its padded address on its own;
@@ -934,9 +973,10 @@ struct FourStepCtx {
 // output costs one LDS read instead of two table reads.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
-          bool Wrap_ = false, bool LdsTw_ = false>
+          bool Wrap_ = false, bool LdsTw_ = false, bool TwPair_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
+    static constexpr bool kTwPair = TwPair_;  // as in SinglePassPolicy
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     // Wrap: tile columns are first + c modulo the (power-of-two) column
     // count, so blocks may start at any column and the last one wraps
@@ -1170,9 +1210,10 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
-          bool Wrap_ = false>
+          bool Wrap_ = false, bool TwPair_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
+    static constexpr bool kTwPair = TwPair_;  // as in SinglePassPolicy
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     static constexpr bool kWrap = Wrap_;    // as in ColumnPolicy (rows modulo n1)
     static constexpr int PS = PS_;

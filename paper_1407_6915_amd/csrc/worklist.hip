@@ -232,7 +232,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
 // items [0, n) of the wide range, grid-stride (every wide tile is the same
 // size, so no cursor is needed).
 using ShWide = Shape<16384, 512, Radices<16, 32, 32>>;
-using PWide = SinglePassPolicy<ShWide, 1, 4, true, 0, false, 4, false, false, false, true>;
+using PWide =
+    SinglePassPolicy<ShWide, 1, 4, true, 0, false, 4, false, false, false, true, true>;
 
 template <int D>
 __global__ void __launch_bounds__(PWide::kThreads) __attribute__((amdgpu_waves_per_eu(4)))
