@@ -54,6 +54,12 @@ ColumnDesc split_column_desc(int config, int variant)
         return ColInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
     case 2:
         return ColInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
+    case 3:
+        return ColInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kLdsTw | kTwPair, 32,
+                       32>::desc(variant);
+    case 4:
+        return ColInst<512, 16, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kLdsTw | kTwPair, 32,
+                       16>::desc(variant);
     default:
         return ColumnDesc{};
     }
@@ -69,6 +75,12 @@ RowDesc split_row_desc(int config, int variant)
         return RowInst<2048, 128, 8, 4, kSplit | kNoHoist | kXcd | kW8, 16, 16, 8>::desc(variant);
     case 2:
         return RowInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4, 32, 32>::desc(variant);
+    case 3:
+        return RowInst<1024, 32, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kTwPair, 32, 32>::desc(
+            variant);
+    case 4:
+        return RowInst<512, 16, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kTwPair, 32, 16>::desc(
+            variant);
     default:
         return RowDesc{};
     }

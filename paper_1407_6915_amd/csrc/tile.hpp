@@ -982,7 +982,6 @@ struct ColumnPolicy {
     // count, so blocks may start at any column and the last one wraps
     static constexpr bool kWrap = Wrap_;
     static constexpr bool kLdsTw = LdsTw_;
-    static_assert(!(kLdsTw && kSplit), "LDS twiddles need the complex exchange layout");
     static_assert(!kLdsTw || Sh::NS > 1, "the LDS twiddles are ordered by the exchange barriers");
     static constexpr int PS = PS_;
     static constexpr bool kPlainLds = false;
@@ -995,9 +994,14 @@ struct ColumnPolicy {
     static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
     static constexpr int kLastR = Sh::Rad::at(Sh::NS - 1);
     static constexpr int kLastNB = Sh::M / kLastR;
+    // exchange elements: complex values, or floats with split exchanges
     static constexpr int kExchElems = (pad(Sh::M - 1) + 1) * C;
     static constexpr int kTwElems = kLdsTw ? kLastR * C : 0;
-    static constexpr int kLdsElems = kExchElems + 2 * kTwElems;
+    // the two twiddle buffers follow the exchange area (offset in complex
+    // values from the LDS base); kLdsElems counts in the exchange's units
+    static constexpr int kTwOffset = kSplit ? (kExchElems + 1) / 2 : kExchElems;
+    static constexpr int kLdsElems = kSplit ? 2 * kTwOffset + 4 * kTwElems
+                                            : kExchElems + 2 * kTwElems;
     static constexpr int kThreads = Sh::T * C;
     using Ctx = FourStepCtx;
     template <int I>
@@ -1067,7 +1071,7 @@ __device__ __forceinline__ void column_lds_twiddles(c32 *lds, FourStepCtx &ctx, 
                                                     int tid)
 {
     if constexpr (Pol::kLdsTw) {
-        c32 *ltw = lds + Pol::kExchElems + (par & 1) * Pol::kTwElems;
+        c32 *ltw = lds + Pol::kTwOffset + (par & 1) * Pol::kTwElems;
         const unsigned mask = (1u << ctx.sh) - 1u;
         for (int e = tid; e < Pol::kTwElems; e += Pol::kThreads) {
             const int r = e / Pol::C, c = e - (e / Pol::C) * Pol::C;

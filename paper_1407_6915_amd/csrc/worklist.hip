@@ -77,27 +77,28 @@ struct Tables {      // per kind, device pointers
 
 constexpr int kThreads = 256;
 
-// routine shapes (streamed global access, twiddles reloaded per task)
+// routine shapes (streamed global access, twiddles reloaded per task and
+// read in pairs)
 using Sh256 = Shape<256, 16, Radices<16, 16>>;
-using P256 = SinglePassPolicy<Sh256, 16, 4, true, 0, false>;
+using P256 = SinglePassPolicy<Sh256, 16, 4, true, 0, false, 1, false, false, false, false, true>;
 using Sh1000 = Shape<1000, 100, Radices<10, 10, 10>>;
 using P1000 = SinglePassPolicy<Sh1000, 2, 4, true, 0, true>;
 using Sh1024 = Shape<1024, 64, Radices<16, 16, 4>>;
-using P1024 = SinglePassPolicy<Sh1024, 4, 4, true, 0, false>;
+using P1024 = SinglePassPolicy<Sh1024, 4, 4, true, 0, false, 1, false, false, false, false, true>;
 using Sh1536 = Shape<1536, 96, Radices<16, 16, 6>>;
-using P1536 = SinglePassPolicy<Sh1536, 2, 4, true, 0, true>;
+using P1536 = SinglePassPolicy<Sh1536, 2, 4, true, 0, true, 1, false, false, false, false, true>;
 using Sh4096 = Shape<4096, 256, Radices<16, 16, 16>>;
-using P4096 = SinglePassPolicy<Sh4096, 1, 4, true, 0, false>;
+using P4096 = SinglePassPolicy<Sh4096, 1, 4, true, 0, false, 1, false, false, false, false, true>;
 using Sh6000 = Shape<6000, 256, Radices<16, 15, 25>>;
 // 6000-point tiles exchange the real parts, then the imaginary parts, through
 // LDS: half the space (25.5 instead of 51 KB), so the 34.8 KB of the 4096-point
 // and two-pass tiles sets the kernel's LDS and 4 workgroups fit a CU instead
 // of 3 (4-5 % faster on a mixed list of every kind; lists of 4096-point
 // segments alone are about 5 % slower under the tighter register budget)
-using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false, 1, false, false, false, true>;
+using P6000 = SinglePassPolicy<Sh6000, 1, 4, true, 0, false, 1, false, false, false, true, true>;
 using Sh256c = Shape<256, 16, Radices<16, 16>>;
-using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true, true>;
-using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true>;
+using PCol256 = ColumnPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true, true, true>;
+using PRow256 = RowPolicy<Sh256c, 16, 4, true, 0, false, 1, false, false, true, true>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kLdsElems =
