@@ -34,6 +34,7 @@ const ColumnDesc kColumns[] = {
     radix32_column_desc(4, 5),
     radix32_column_desc(6, 6),
     split_column_desc(4, 7),
+    radix32_column_desc(8, 8),
     radix32_column_desc(0, 0),
     ColInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     ColInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
@@ -50,6 +51,7 @@ const ColumnDesc kColumns[] = {
     radix32_column_desc(3, 13),
     radix32_column_desc(5, 14),
     split_column_desc(3, 15),
+    radix32_column_desc(7, 16),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kFrames | kShifted | kLdsTw, 16, 16,
             8>::desc(0),
     ColInst<2048, 128, 8, 4, kNoHoist, 16, 16, 8>::desc(1),
@@ -78,6 +80,7 @@ const RowDesc kRows[] = {
     radix32_row_desc(2, 4),
     radix32_row_desc(4, 5),
     split_row_desc(4, 6),
+    radix32_row_desc(6, 7),
     radix32_row_desc(0, 0),
     RowInst<1024, 64, 16, 4, kNoHoist | kXcd, 16, 16, 4>::desc(1),
     RowInst<1024, 64, 8, 4, kXcd, 16, 16, 4>::desc(2),
@@ -93,6 +96,7 @@ const RowDesc kRows[] = {
     split_row_desc(2, 12),
     radix32_row_desc(3, 13),
     split_row_desc(3, 14),
+    radix32_row_desc(5, 15),
     RowInst<2048, 128, 8, 4, kNoHoist | kShifted, 16, 16, 8>::desc(0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),

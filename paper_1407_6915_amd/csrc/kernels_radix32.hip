@@ -22,8 +22,11 @@ ColumnDesc radix32_column_desc(int config, int variant)
                        kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
                        32>::desc(variant);
     case 1:
+        // streamed (non-temporal) access: 5.84-5.87 ms per 8 GiB of 2^18-point
+        // segments with the row tile's against 6.13 cached (at 1024 points the
+        // streamed forms, configs 7 here and 5 below, are 3-10 % slower)
         return ColInst<512, 16, 16, 4,
-                       kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
+                       kNT | kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
                        16>::desc(variant);
     case 2:
         return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
@@ -35,6 +38,12 @@ ColumnDesc radix32_column_desc(int config, int variant)
         return ColInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kLdsTw, 32, 32>::desc(variant);
     case 6:
         return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kLdsTw, 32, 16>::desc(variant);
+    case 7:
+        return ColInst<1024, 32, 16, 4, kNT | kNoHoist | kXcd | kW2 | kLdsTw | kTwPair, 32,
+                       32>::desc(variant);
+    case 8:
+        return ColInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kLdsTw | kTwPair, 32, 16>::desc(
+            variant);
     default:
         return ColumnDesc{};
     }
@@ -48,14 +57,19 @@ RowDesc radix32_row_desc(int config, int variant)
         return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32, 32>::desc(
             variant);
     case 1:
-        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32, 16>::desc(
-            variant);
+        return RowInst<512, 16, 16, 4, kNT | kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32,
+                       16>::desc(variant);
     case 2:
         return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     case 3:
         return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2, 32, 32>::desc(variant);
     case 4:
         return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2, 32, 16>::desc(variant);
+    case 5:
+        return RowInst<1024, 32, 16, 4, kNT | kNoHoist | kXcd | kW2 | kTwPair, 32, 32>::desc(
+            variant);
+    case 6:
+        return RowInst<512, 16, 16, 4, kNoHoist | kXcd | kW2 | kTwPair, 32, 16>::desc(variant);
     default:
         return RowDesc{};
     }
