@@ -19,10 +19,12 @@ namespace fs {
 // offsets (kIndexed); one row per length carries each of these forms;
 // the column pass splits W_N^{n2 k1} into a per-butterfly lookup and a
 // per-tile LDS table (kLdsTw, ColumnPolicy); stages that reload their
-// twiddles read them as pairs (kTwPair, tw_pair_low)
+// twiddles read them as pairs (kTwPair, tw_pair_low); both passes also come
+// in a form with Y in blocks of 16 columns (kYBlocked, see kYBlock), which a
+// plan takes when its column and row tiles both have it
 constexpr int kNT = 1, kNoHoist = 2, kXcd = 4, kHoistLast = 8, kW2 = 16, kPlainLane = 32,
               kSplit = 64, kW4 = 128, kW8 = 256, kFrames = 1024, kShifted = 2048,
-              kIndexed = 4096, kLdsTw = 8192, kTwPair = 16384;
+              kIndexed = 4096, kLdsTw = 8192, kTwPair = 16384, kYBlocked = 32768;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -52,6 +54,24 @@ struct ColInst {
                               (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
                               (F & kSplit) != 0, true, (F & kLdsTw) != 0,
                               (F & kTwPair) != 0>;
+    using PolB = ColumnPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                              (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
+                              (F & kSplit) != 0, false, (F & kLdsTw) != 0,
+                              (F & kTwPair) != 0, true>;
+    static void launch_yblocked(int dir, const void *in, void *ybuf, const void *tw,
+                                const void *tl, const void *th, int sh, int n2,
+                                uint64_t batch, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_columns_kernel<Sh, PolB, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw,
+                               (const c32 *)tl, (const c32 *)th, sh, n2, batch);
+        else
+            hipLaunchKernelGGL((four_step_columns_kernel<Sh, PolB, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw,
+                               (const c32 *)tl, (const c32 *)th, sh, n2, batch);
+    }
     static void launch_shifted(int dir, const void *in, void *ybuf, const void *tw,
                                const void *tl, const void *th, int sh, int n2, uint64_t batch,
                                int shift, unsigned grid, hipStream_t s)
@@ -140,6 +160,11 @@ struct ColInst {
             d.kernel_indexed[0] = (const void *)&four_step_columns_indexed_kernel<Sh, PolW, -1>;
             d.kernel_indexed[1] = (const void *)&four_step_columns_indexed_kernel<Sh, PolW, 1>;
         }
+        if constexpr ((F & kYBlocked) != 0) {
+            d.launch_yblocked = &launch_yblocked;
+            d.kernel_yblocked[0] = (const void *)&four_step_columns_kernel<Sh, PolB, -1>;
+            d.kernel_yblocked[1] = (const void *)&four_step_columns_kernel<Sh, PolB, 1>;
+        }
         return d;
     }
 };
@@ -153,6 +178,20 @@ struct RowInst {
     using PolW = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
                            (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
                            (F & kSplit) != 0, true, (F & kTwPair) != 0>;
+    using PolB = RowPolicy<Sh, C, PS, (F & kNT) != 0, hoist_mask<sizeof...(Rs), F>(),
+                           (F & kXcd) != 0, waves<F>(), (F & kPlainLane) != 0,
+                           (F & kSplit) != 0, false, (F & kTwPair) != 0, true>;
+    static void launch_yblocked(int dir, const void *ybuf, void *out, const void *tw, int n1,
+                                uint64_t batch, unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_rows_kernel<Sh, PolB, -1>), g, b, 0, s,
+                               (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch);
+        else
+            hipLaunchKernelGGL((four_step_rows_kernel<Sh, PolB, 1>), g, b, 0, s,
+                               (const c32 *)ybuf, (c32 *)out, (const c32 *)tw, n1, batch);
+    }
     static void launch_shifted(int dir, const void *ybuf, void *out, const void *tw, int n1,
                                uint64_t batch, int shift, unsigned grid, hipStream_t s)
     {
@@ -214,6 +253,11 @@ struct RowInst {
             d.launch_indexed = &launch_indexed;
             d.kernel_indexed[0] = (const void *)&four_step_rows_indexed_kernel<Sh, PolW, -1>;
             d.kernel_indexed[1] = (const void *)&four_step_rows_indexed_kernel<Sh, PolW, 1>;
+        }
+        if constexpr ((F & kYBlocked) != 0) {
+            d.launch_yblocked = &launch_yblocked;
+            d.kernel_yblocked[0] = (const void *)&four_step_rows_kernel<Sh, PolB, -1>;
+            d.kernel_yblocked[1] = (const void *)&four_step_rows_kernel<Sh, PolB, 1>;
         }
         return d;
     }

@@ -11,13 +11,18 @@ using namespace fs;
 // default column tiles split W_N^{n2 k1} through LDS (kLdsTw), and the 512-
 // and 1024-point tiles (kernels_radix32.hip) also read their second stage's
 // twiddles in pairs (kTwPair); the forms without these stay as variants.
+// The default 128-, 256- and 512-point tiles also come in the form with Y
+// in blocks of 16 columns (kYBlocked): plans of two such tiles take it
+// (65536 points: 5.71-5.73 ms per 8 GiB against 5.94-6.13; at 1024 points
+// the blocked form was 2-3 % slower).
 //                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
-    ColInst<128, 8, 16, 4, kFrames | kShifted | kLdsTw, 16, 8>::desc(0),
+    ColInst<128, 8, 16, 4, kFrames | kShifted | kLdsTw | kYBlocked, 16, 8>::desc(0),
     ColInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     ColInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
     ColInst<128, 8, 16, 4, 0, 16, 8>::desc(3),
-    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames | kShifted | kLdsTw, 16, 16>::desc(0),
+    ColInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kFrames | kShifted | kLdsTw | kYBlocked, 16,
+            16>::desc(0),
     ColInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     ColInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     ColInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),
@@ -62,10 +67,10 @@ const ColumnDesc kColumns[] = {
 };
 
 const RowDesc kRows[] = {
-    RowInst<128, 8, 16, 4, kShifted, 16, 8>::desc(0),
+    RowInst<128, 8, 16, 4, kShifted | kYBlocked, 16, 8>::desc(0),
     RowInst<128, 8, 32, 4, kXcd, 16, 8>::desc(1),
     RowInst<128, 8, 32, 4, kXcd | kPlainLane, 16, 8>::desc(2),
-    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kShifted, 16, 16>::desc(0),
+    RowInst<256, 16, 16, 4, kNT | kXcd | kHoistLast | kShifted | kYBlocked, 16, 16>::desc(0),
     RowInst<256, 16, 16, 4, kXcd, 16, 16>::desc(1),
     RowInst<256, 16, 32, 4, kNT | kXcd, 16, 16>::desc(2),
     RowInst<256, 16, 16, 4, kNT | kXcd, 16, 16>::desc(3),

@@ -26,8 +26,9 @@ ColumnDesc radix32_column_desc(int config, int variant)
         // segments with the row tile's against 6.13 cached (at 1024 points the
         // streamed forms, configs 7 here and 5 below, are 3-10 % slower)
         return ColInst<512, 16, 16, 4,
-                       kNT | kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair, 32,
-                       16>::desc(variant);
+                       kNT | kNoHoist | kXcd | kW2 | kFrames | kShifted | kLdsTw | kTwPair |
+                           kYBlocked,
+                       32, 16>::desc(variant);
     case 2:
         return ColInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);
     case 3:
@@ -57,7 +58,8 @@ RowDesc radix32_row_desc(int config, int variant)
         return RowInst<1024, 32, 16, 4, kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32, 32>::desc(
             variant);
     case 1:
-        return RowInst<512, 16, 16, 4, kNT | kNoHoist | kXcd | kW2 | kShifted | kTwPair, 32,
+        return RowInst<512, 16, 16, 4,
+                       kNT | kNoHoist | kXcd | kW2 | kShifted | kTwPair | kYBlocked, 32,
                        16>::desc(variant);
     case 2:
         return RowInst<512, 32, 16, 4, kXcd | kW2, 16, 32>::desc(variant);

@@ -80,6 +80,8 @@ struct ColumnDesc {
     const void *kernel_shifted[2];
     col_indexed_launch_fn launch_indexed;  // segments at listed offsets
     const void *kernel_indexed[2];
+    col_launch_fn launch_yblocked;  // as launch, Y in blocks of 16 columns
+    const void *kernel_yblocked[2];
 };
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.
@@ -92,6 +94,8 @@ struct RowDesc {
     const void *kernel_shifted[2];
     row_indexed_launch_fn launch_indexed;  // segments at listed offsets
     const void *kernel_indexed[2];
+    row_launch_fn launch_yblocked;  // as launch, Y in blocks of 16 columns
+    const void *kernel_yblocked[2];
 };
 
 const SinglePassDesc *single_pass_table(int *count);

@@ -489,6 +489,11 @@ int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant
         p->kind = Plan::FOURSTEP;
         p->n1 = (uint64_t)p->col->n1;
         p->n2 = (uint64_t)p->row->n2;
+        // Y in blocks of 16 columns where both tiles have that form
+        // (FFTSEG_Y_LAYOUT=plain keeps the input's layout, for comparison)
+        const char *yl = getenv("FFTSEG_Y_LAYOUT");
+        p->y_blocked = p->col->launch_yblocked && p->row->launch_yblocked &&
+                       !(yl && strcmp(yl, "plain") == 0);
         // (one line more: Y may start at the input's offset within a line)
         p->sub_batch = std::min<uint64_t>(batch, max_sub_samples / n);
         p->scratch_bytes = (p->sub_batch * n + kLineSamples) * sizeof(c32);
@@ -836,8 +841,11 @@ int plan_enqueue(Plan *p, const void *in, void *out, uint64_t batch, hipStream_t
                                          p->device, p->grid_mult);
             const unsigned gb = grid_for(rd->kernel[dir > 0], rd->threads * rd->rows, tb,
                                          p->device, p->grid_mult);
-            cd->launch(dir, x, p->scratch, p->tw, p->tl, p->th, p->sh, (int)p->n2, sb, ga, s);
-            rd->launch(dir, p->scratch, y, p->tw2, (int)p->n1, sb, gb, s);
+            (p->y_blocked ? cd->launch_yblocked : cd->launch)(dir, x, p->scratch, p->tw, p->tl,
+                                                              p->th, p->sh, (int)p->n2, sb,
+                                                              ga, s);
+            (p->y_blocked ? rd->launch_yblocked : rd->launch)(dir, p->scratch, y, p->tw2,
+                                                              (int)p->n1, sb, gb, s);
         }
         break;
     }
@@ -912,14 +920,15 @@ int plan_describe(const Plan *p, std::string &js)
                  "\"n1\":%llu,\"n2\":%llu,\"radices_n1\":%s,\"radices_n2\":%s,"
                  "\"columns_per_workgroup\":%d,\"rows_per_workgroup\":%d,"
                  "\"column_variant\":%d,\"row_variant\":%d,\"grid_mult\":%d,"
-                 "\"lds_bytes\":[%d,%d],\"sub_batch\":%llu,\"scratch_bytes\":%zu}",
+                 "\"lds_bytes\":[%d,%d],\"sub_batch\":%llu,\"scratch_bytes\":%zu,"
+                 "\"y_blocked\":%d}",
                  (unsigned long long)p->n, (unsigned long long)p->batch, p->dir,
                  (unsigned long long)p->n1, (unsigned long long)p->n2,
                  rad(p->col->radices, p->col->nrad).c_str(),
                  rad(p->row->radices, p->row->nrad).c_str(), p->col->cols, p->row->rows,
                  p->col->variant, p->row->variant, p->grid_mult,
                  p->col->lds_bytes, p->row->lds_bytes, (unsigned long long)p->sub_batch,
-                 p->scratch_bytes);
+                 p->scratch_bytes, (int)p->y_blocked);
         break;
     case Plan::REAL:
         snprintf(buf, sizeof buf,

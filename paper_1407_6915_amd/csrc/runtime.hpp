@@ -31,6 +31,7 @@ struct Plan {
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     uint64_t sub_batch = 0;
+    bool y_blocked = false;     // FOURSTEP: Y in blocks of 16 columns between the passes
     int grid_mult = 0;          // 0: one workgroup per tile
     bool used = false;
     bool last_stream_valid = false;

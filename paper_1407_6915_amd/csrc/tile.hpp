@@ -949,6 +949,15 @@ __device__ __forceinline__ uint64_t tile_of(uint64_t sweep_base, unsigned w, uns
     return sweep_base + w;
 }
 
+// Y between the two passes: in the input's layout, Y[k1][n2] at k1 N2 + n2,
+// or (policies with YBlk) in blocks of kYBlock columns, at
+// ((n2 / kYBlock) N1 + k1) kYBlock + n2 mod kYBlock.  Blocked, a column tile
+// of 16 columns writes whole runs of 16 N1 samples instead of 128-byte
+// pieces N2 samples apart, and a row tile of 16 rows reads runs of 256
+// samples instead of whole rows; the plan pairs blocked column and row
+// tiles only (the forms that wrap round keep the input's layout).
+constexpr int kYBlock = 16;
+
 struct FourStepCtx {
     const c32 *x;   // pass A: segment input;     pass B: segment of Y
     c32 *y;         // pass A: segment of Y;      pass B: segment output
@@ -973,9 +982,10 @@ struct FourStepCtx {
 // output costs one LDS read instead of two table reads.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
-          bool Wrap_ = false, bool LdsTw_ = false, bool TwPair_ = false>
+          bool Wrap_ = false, bool LdsTw_ = false, bool TwPair_ = false, bool YBlk_ = false>
 struct ColumnPolicy {
     static constexpr int C = C_;
+    static constexpr bool kYBlk = YBlk_ && !Wrap_;  // Y in blocks of kYBlock columns
     static constexpr bool kTwPair = TwPair_;  // as in SinglePassPolicy
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     // Wrap: tile columns are first + c modulo the (power-of-two) column
@@ -1004,6 +1014,14 @@ struct ColumnPolicy {
                                             : kExchElems + 2 * kTwElems;
     static constexpr int kThreads = Sh::T * C;
     using Ctx = FourStepCtx;
+    // index of Y[k1][n2] (see kYBlock)
+    static __device__ __forceinline__ size_t y_at(unsigned k1, unsigned n2, const Ctx &ctx)
+    {
+        if constexpr (kYBlk)
+            return ((size_t)(n2 / kYBlock) * (unsigned)Sh::M + k1) * kYBlock + n2 % kYBlock;
+        else
+            return (size_t)k1 * ctx.n2 + n2;
+    }
     template <int I>
     static __device__ __forceinline__ int col(int tid) { return tid % C; }
     template <int I>
@@ -1037,7 +1055,7 @@ struct ColumnPolicy {
 #pragma unroll
                     for (int r = 0; r < St::R; ++r) {
                         const unsigned k1 = (unsigned)(b + r * St::NB);
-                        gstore<kNT>(ctx.y + (size_t)k1 * ctx.n2 + n2,
+                        gstore<kNT>(ctx.y + y_at(k1, n2, ctx),
                                     twiddle<D>(v[u * St::R + r], cmul(a, bw[r * C])));
                     }
                 }
@@ -1053,8 +1071,7 @@ struct ColumnPolicy {
                     const unsigned k1 = (unsigned)(b + r * St::NB);
                     const unsigned m = n2 * k1;
                     const c32 w = cmul(ctx.th[m >> ctx.sh], ctx.tl[m & mask]);
-                    gstore<kNT>(ctx.y + (size_t)k1 * ctx.n2 + n2,
-                                twiddle<D>(v[u * St::R + r], w));
+                    gstore<kNT>(ctx.y + y_at(k1, n2, ctx), twiddle<D>(v[u * St::R + r], w));
                 }
             }
         }
@@ -1214,9 +1231,10 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // transposed store X[k1 + N1 k2] writes C consecutive k1 per k2.
 template <class Sh, int C_, int PS_, bool NT_ = false, int HoistMask_ = -1,
           bool Xcd_ = false, int Waves_ = 1, bool PlainLane_ = false, bool Split_ = false,
-          bool Wrap_ = false, bool TwPair_ = false>
+          bool Wrap_ = false, bool TwPair_ = false, bool YBlk_ = false>
 struct RowPolicy {
     static constexpr int C = C_;
+    static constexpr bool kYBlk = YBlk_ && !Wrap_;  // as in ColumnPolicy
     static constexpr bool kTwPair = TwPair_;  // as in SinglePassPolicy
     static constexpr bool kSplit = Split_;  // as in SinglePassPolicy
     static constexpr bool kWrap = Wrap_;    // as in ColumnPolicy (rows modulo n1)
@@ -1282,8 +1300,18 @@ __device__ __forceinline__ void row_tile(c32 *lds, const c32 *__restrict__ tw, i
     const int t = Pol::template thr<0>(tid);
     c32 v[Sh::kMaxE];
     using S0 = Stage<Sh, 0, 1>;
-    const c32 *yr = y + (size_t)(Pol::kWrap ? ((first + c) & (n1 - 1)) : (first + c)) * Sh::M;
-    st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
+    if constexpr (Pol::kYBlk) {
+        // Y in blocks of kYBlock columns (row k1 = first + c)
+        const c32 *yr = y + (size_t)(first + c) * kYBlock;
+        const size_t blk = (size_t)n1 * kYBlock;
+        st_gather<S0, Sh>(v, t, [&](int i) {
+            return gload<Pol::kNT>(yr + (size_t)(i / kYBlock) * blk + i % kYBlock);
+        });
+    } else {
+        const c32 *yr =
+            y + (size_t)(Pol::kWrap ? ((first + c) & (n1 - 1)) : (first + c)) * Sh::M;
+        st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(yr + i); });
+    }
     if constexpr (Pol::kSplit)
         tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
                                          ctx);

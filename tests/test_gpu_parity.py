@@ -109,6 +109,9 @@ def test_four_step_tiles_walk_several_tiles(monkeypatch, n, b):
         announce("n=%d column variant %d row variant %d batch=%d grid_mult=1" % (n, c, r, b))
         for d in (fs.FORWARD, fs.INVERSE):
             with fs.Plan(n, b, d, split_variants=(c, r)) as p:
+                if (c, r) == (0, 0):
+                    # the default tiles below 1024 points keep Y in 16-column blocks
+                    assert p.describe()["y_blocked"] == int(n1 < 1024 and n2 < 1024)
                 y = p.exec(xd).cpu().numpy().reshape(b, n)
             e = oracle.rel_l2(y, ref[d])
             assert np.all(e <= oracle.tolerance(n)), (c, r, d, float(e.max()))
