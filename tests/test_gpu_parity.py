@@ -362,3 +362,28 @@ def test_plan_describe():
     assert d["kind"] == "four_step" and d["n1"] * d["n2"] == 1 << 20
     d = fs.Plan(3 ** 9, 2).describe()
     assert d["kind"] == "radix_stages"
+
+
+@pytest.mark.parametrize("n,b,sub", [(1 << 16, 7, 2), (1 << 18, 5, 2), (1 << 20, 5, 2)])
+@pytest.mark.parametrize("lead", [0, 3])
+def test_two_pass_plans_across_sub_batches(monkeypatch, n, b, sub, lead):
+    """Two-pass plans whose batch runs as several sub-batches through the
+    one scratch buffer (a ragged last one), with Y in 16-column blocks where
+    the plan's tiles have that form, from bases on a line and `lead` samples
+    past one."""
+    import torch
+    monkeypatch.setenv("FFTSEG_SUB_SAMPLES", str(sub * n))
+    x = noise(n, b, seed=n + 41)
+    for d in (fs.FORWARD, fs.INVERSE):
+        announce("n=%d batch=%d sub-batch=%d lead=%d dir=%d" % (n, b, sub, lead, d))
+        xd = torch.zeros(n * b + 16, dtype=torch.complex64, device="cuda")
+        xd[lead:lead + n * b] = torch.from_numpy(x.reshape(-1))
+        yd = torch.zeros_like(xd)
+        with fs.Plan(n, b, d) as p:
+            desc = p.describe()
+            assert desc["sub_batch"] == sub
+            p.exec(xd[lead:lead + n * b], yd[lead:lead + n * b])
+        y = yd.cpu().numpy()
+        assert not y[:lead].any() and not y[lead + n * b:].any()
+        check(n, y[lead:lead + n * b].reshape(b, n), x, d,
+              what="y_blocked %d" % desc["y_blocked"])
