@@ -160,8 +160,10 @@ const char *fft_last_error(void);
 int fft_plan_factorize(size_t n, int *radices, int max);
 
 /* Describe the plan as a JSON object (kind, kernels, radices, split,
- * threads, LDS bytes, scratch bytes) into buf (NUL terminated, truncated to
- * len).  Returns the full length needed, or a negative fft_status_t. */
+ * threads, LDS bytes, scratch bytes; for two-pass plans also the sub-batch
+ * and whether the intermediate array is kept in blocks of 16 columns,
+ * "y_blocked") into buf (NUL terminated, truncated to len).  Returns the
+ * full length needed, or a negative fft_status_t. */
 int fft_plan_describe(fft_plan_t plan, char *buf, size_t len);
 
 /* Bytes of device scratch the plan owns (0 for single-pass plans). */
