@@ -39,6 +39,7 @@ def run_frames(n, x, hop, n_frames, window, direction=fs.FORWARD, batch=None):
     (1 << 16, 1 << 14, 5),  # two-pass lengths: read by the column pass
     (1 << 15, 1000, 6),
     (1 << 18, 70001, 4),
+    (1 << 20, 1 << 18, 3),  # the 1024-point column tiles' frame form
     (3 ** 9, 5000, 4),      # radix-stage fallback
     (1, 1, 11),             # identity length
 ])
