@@ -61,6 +61,9 @@ int frames_enqueue(Plan *p, const c32 *in, c32 *out, uint64_t frames, uint64_t h
         const ColumnDesc *cd = p->col;
         const RowDesc *rd = p->row;
         const int dir = p->dir;
+        // Y in 16-column blocks where the plan keeps it so and the column
+        // tile has the blocked frame form
+        const bool yb = p->y_blocked && cd->launch_frames_yblocked;
         for (uint64_t s0 = 0; s0 < frames; s0 += p->sub_batch) {
             const uint64_t sb = std::min(p->sub_batch, frames - s0);
             const uint64_t ta = sb * (p->n2 / (uint64_t)cd->cols);
@@ -69,9 +72,11 @@ int frames_enqueue(Plan *p, const c32 *in, c32 *out, uint64_t frames, uint64_t h
                                          p->device, p->grid_mult);
             const unsigned gb = grid_for(rd->kernel[dir > 0], rd->threads * rd->rows, tb,
                                          p->device, p->grid_mult);
-            cd->launch_frames(dir, in + s0 * hop, p->scratch, p->tw, p->tl, p->th, p->sh,
-                              (int)p->n2, sb, hop, window, ga, s);
-            rd->launch(dir, p->scratch, out + s0 * n, p->tw2, (int)p->n1, sb, gb, s);
+            (yb ? cd->launch_frames_yblocked : cd->launch_frames)(
+                dir, in + s0 * hop, p->scratch, p->tw, p->tl, p->th, p->sh, (int)p->n2, sb, hop,
+                window, ga, s);
+            (yb ? rd->launch_yblocked : rd->launch)(dir, p->scratch, out + s0 * n, p->tw2,
+                                                    (int)p->n1, sb, gb, s);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)

@@ -114,6 +114,21 @@ struct ColInst {
                                (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
                                (const c32 *)th, sh, n2, batch, hop, window);
     }
+    static void launch_frames_yblocked(int dir, const void *in, void *ybuf, const void *tw,
+                                       const void *tl, const void *th, int sh, int n2,
+                                       uint64_t batch, uint64_t hop, const float *window,
+                                       unsigned grid, hipStream_t s)
+    {
+        const dim3 g(grid), b(Pol::kThreads);
+        if (dir < 0)
+            hipLaunchKernelGGL((four_step_columns_frames_kernel<Sh, PolB, -1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, hop, window);
+        else
+            hipLaunchKernelGGL((four_step_columns_frames_kernel<Sh, PolB, 1>), g, b, 0, s,
+                               (const c32 *)in, (c32 *)ybuf, (const c32 *)tw, (const c32 *)tl,
+                               (const c32 *)th, sh, n2, batch, hop, window);
+    }
     static void launch_indexed(int dir, const void *in, void *ybuf, const void *tw,
                                const void *tl, const void *th, int sh, int n2,
                                const uint64_t *offs, uint64_t batch, unsigned grid,
@@ -164,6 +179,13 @@ struct ColInst {
             d.launch_yblocked = &launch_yblocked;
             d.kernel_yblocked[0] = (const void *)&four_step_columns_kernel<Sh, PolB, -1>;
             d.kernel_yblocked[1] = (const void *)&four_step_columns_kernel<Sh, PolB, 1>;
+        }
+        if constexpr ((F & kYBlocked) != 0 && (F & kFrames) != 0) {
+            d.launch_frames_yblocked = &launch_frames_yblocked;
+            d.kernel_frames_yblocked[0] =
+                (const void *)&four_step_columns_frames_kernel<Sh, PolB, -1>;
+            d.kernel_frames_yblocked[1] =
+                (const void *)&four_step_columns_frames_kernel<Sh, PolB, 1>;
         }
         return d;
     }

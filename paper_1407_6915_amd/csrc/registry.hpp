@@ -82,6 +82,8 @@ struct ColumnDesc {
     const void *kernel_indexed[2];
     col_launch_fn launch_yblocked;  // as launch, Y in blocks of 16 columns
     const void *kernel_yblocked[2];
+    col_frames_launch_fn launch_frames_yblocked;  // as launch_frames, Y blocked
+    const void *kernel_frames_yblocked[2];
 };
 
 // Four-step pass B: N2-point row transforms, C rows per workgroup.
