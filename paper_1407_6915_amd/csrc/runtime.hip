@@ -411,17 +411,19 @@ unsigned grid_for(const void *kernel, int threads, uint64_t work_groups, int dev
 constexpr int kDefaultGridMult = 8;
 constexpr int kTwoPassGridMult = 32;  // four-step passes without a measured choice
 
-// Four-step passes: the measured best grid by column-tile length (interleaved
-// A/B runs at 8 GiB; 128 is one workgroup per tile of a 4 GiB sub-batch at
-// 256 and 512 points)
+// Four-step passes: the measured best grid by column-tile length (sweeps at
+// 8 GiB; 128 resident waves per CU is one workgroup per tile of a 4 GiB
+// sub-batch from 128- to 1024-point columns, which beat the persistent
+// grids of 16-64 once the tiles' twiddle reads were cut: 2^15 points
+// 6.21 ms against 6.45 at 32, 2^20 6.42-6.44 against 6.50-6.78 at 64)
 int two_pass_grid_mult(uint64_t n1)
 {
     switch (n1) {
+    case 128:
     case 256:
     case 512:
-        return 128;
     case 1024:
-        return 64;
+        return 128;
     default:
         return kTwoPassGridMult;
     }
