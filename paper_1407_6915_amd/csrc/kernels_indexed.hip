@@ -36,13 +36,13 @@ const SinglePassDesc kIdx4096[] = {
     SpInst<4096, 128, 2, 4, kClassic | kIndexed, 16, 16, 16>::desc(1, 32),
 };
 const SinglePassDesc kIdx6000[] = {
-    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kTwPair | kW4 | kIndexed, 16, 15, 25>::desc(0, 32),
+    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kTwPair | kW4 | kIndexed, 16, 15, 25>::desc(0, 0),
     SpInst<6000, 400, 1, 4, kClassic | kNT | kIndexed, 16, 15, 25>::desc(1, 32),
     SpInst<6000, 400, 1, 4, kClassic | kIndexed, 16, 15, 25>::desc(2, 32),
 };
 const SinglePassDesc kIdx16384[] = {
     SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair | kIndexed, 16, 32, 32>::desc(
-        0, 32),
+        0, 0),
 };
 
 // the 65536-point two-pass tiles (256 x 256), as the plan's defaults

@@ -66,7 +66,7 @@ const SinglePassDesc kTable[] = {
     SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(6, 16),
     SpInst<8192, 512, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 16, 16, 2>::desc(7, 32),
     split_desc(6, 8, 32),
-    split_desc(0, 0, 32),
+    split_desc(0, 0, 0),  // one workgroup per segment: 2.95-2.97 ms against 3.19-3.20 at 32
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(1, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),
     SpInst<16384, 512, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(3, 32),
@@ -86,8 +86,10 @@ const SinglePassDesc kTable[] = {
     SpInst<1536, 96, 2, 4, kClassic | kNT, 16, 16, 6>::desc(3, 64),
     // twiddles reloaded per segment and read in pairs, registers for two
     // workgroups per CU (79 VGPRs, three workgroups fit the LDS): 4.8-4.9
-    // TB/s against 4.1-4.2 for the plainly written kernel (variant 7)
-    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 15, 25>::desc(0, 32),
+    // TB/s against 4.1-4.2 for the plainly written kernel (variant 7); one
+    // workgroup per segment, as nothing stays in registers across segments
+    // (3.21 ms per 8 GiB against 3.41-3.46 on a persistent grid of 32)
+    SpInst<6000, 400, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 15, 25>::desc(0, 0),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist, 16, 15, 25>::desc(1, 0),
     SpInst<6000, 300, 1, 4, kNT | kNoHoist | kAux, 20, 20, 15>::desc(2, 32),
     SpInst<6000, 400, 1, 4, kNT | kNoHoist | kPlain, 16, 15, 25>::desc(3, 32),

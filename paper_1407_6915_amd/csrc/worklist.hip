@@ -119,8 +119,10 @@ static_assert(PCol256::kThreads == kThreads && PRow256::kThreads == kThreads,
 // than 4 (with one 65536-point block per task, more of a segment's blocks run
 // at once) and than 1 (twice the atomics)
 constexpr uint32_t kClaim = 2;
-// persistent grid of the wide launch: resident workgroup waves per CU
-constexpr int kWideGridMult = 32;
+// grid of the wide launch: one workgroup per 16384-point segment (its tile
+// re-reads its twiddles per segment, so a persistent grid keeps nothing in
+// registers; 0 = no cap, as FFTSEG_GRID_MULT=0)
+constexpr int kWideGridMult = 0;
 // grid of the two work-list launches: 4 x the resident workgroups (the
 // extra ones start as the first finish and claim what is left; measured
 // 2-3 % faster on the uneven workload than exactly one resident wave)
