@@ -413,9 +413,10 @@ constexpr int kTwoPassGridMult = 32;  // four-step passes without a measured cho
 
 // Four-step passes: the measured best grid by column-tile length (sweeps at
 // 8 GiB; 128 resident waves per CU is one workgroup per tile of a 4 GiB
-// sub-batch from 128- to 1024-point columns, which beat the persistent
+// sub-batch from 128- to 2048-point columns, which beat the persistent
 // grids of 16-64 once the tiles' twiddle reads were cut: 2^15 points
-// 6.21 ms against 6.45 at 32, 2^20 6.42-6.44 against 6.50-6.78 at 64)
+// 6.21 ms against 6.45 at 32, 2^20 6.42-6.44 against 6.50-6.78 at 64,
+// 2^22 9.40 against 9.63 at 32)
 int two_pass_grid_mult(uint64_t n1)
 {
     switch (n1) {
@@ -423,6 +424,7 @@ int two_pass_grid_mult(uint64_t n1)
     case 256:
     case 512:
     case 1024:
+    case 2048:
         return 128;
     default:
         return kTwoPassGridMult;
