@@ -57,6 +57,7 @@ const SinglePassDesc kTable[] = {
     SpInst<4096, 256, 1, 0, kPrefetch | kNT, 16, 16, 16>::desc(11, 32),
     SpInst<4096, 512, 1, 4, kPrefetch | kNT, 8, 8, 8, 8>::desc(12, 32),
     pad32_desc(0, 13, 64),
+    pad32_desc(4, 14, 32),
     pad32_desc(2, 0, 16),
     SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(1, 32),
     SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(2, 32),

@@ -427,6 +427,9 @@ __device__ __forceinline__ int opaque_lane()
     return t;
 }
 
+// LDS layout code for an XOR swizzle instead of a pad shift (SinglePassPolicy)
+constexpr int kLdsXor = -1;
+
 // ---------------------------------------------------------------------------
 // Single pass: S whole segments per workgroup, each owned by T threads.
 //   lane mapping: segment slot = tid / T, thread t = tid % T (all stages);
@@ -460,8 +463,20 @@ struct SinglePassPolicy {
     static constexpr bool kPartial = Partial_;
     static constexpr int kWaves = Waves_;
     static constexpr bool hoists(int stage) { return (kHoistMask >> stage) & 1; }
-    static constexpr int pad(int i) { return PS > 0 ? i + (i >> PS) : i; }
-    static constexpr int kSegStride = pad(Sh::M - 1) + 1;
+    // LDS layout of a segment: one pad element every 2^PS (PS > 0), none
+    // (PS = 0), or (PS = kLdsXor) an XOR swizzle that permutes each run of
+    // 32 elements by the bits above it, i ^ ((i >> 5) mod 32): strides of 16
+    // and 256 elements then spread over all 32 eight-byte bank slots, with no
+    // gaps in the layout.  The swizzle needs per-element addresses (the
+    // plainly written stages), not the base-plus-offset runs of LdsRun.
+    static constexpr int pad(int i)
+    {
+        return PS > 0 ? i + (i >> PS) : PS == kLdsXor ? (i ^ ((i >> 5) & 31)) : i;
+    }
+    static_assert(PS != kLdsXor || kClassic || kPlainLds, "the swizzle needs per-element addresses");
+    static_assert(PS != kLdsXor || Sh::M % 32 == 0, "the swizzle permutes whole runs of 32");
+    // the swizzle is not monotone: its last element is not its largest
+    static constexpr int kSegStride = PS == kLdsXor ? Sh::M : pad(Sh::M - 1) + 1;
     static constexpr int kLdsElems = Sh::NS > 1 ? S * kSegStride : 1;
     static constexpr int kThreads = Sh::T * S;
 
