@@ -14,7 +14,10 @@ using namespace fs;
 // The default 128-, 256- and 512-point tiles also come in the form with Y
 // in blocks of 16 columns (kYBlocked): plans of two such tiles take it
 // (65536 points: 5.71-5.73 ms per 8 GiB against 5.94-6.13; at 1024 points
-// the blocked form was 2-3 % slower).
+// the blocked form was 2-3 % slower).  The default 2048-point row tile has
+// 16 rows and split exchanges (kernels_split.hip): its transposed store
+// writes whole lines (2^22 points: 8.37 ms per 8 GiB against 9.35 with 8
+// rows); the 16-column split column tile spills and stays a variant.
 //                          M     T    C  PS  F                   radices       variant
 const ColumnDesc kColumns[] = {
     ColInst<128, 8, 16, 4, kFrames | kShifted | kLdsTw | kYBlocked, 16, 8>::desc(0),
@@ -64,6 +67,7 @@ const ColumnDesc kColumns[] = {
     split_column_desc(1, 3),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(4),
     ColInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kLdsTw | kTwPair, 16, 16, 8>::desc(5),
+    split_column_desc(5, 6),
 };
 
 const RowDesc kRows[] = {
@@ -102,11 +106,12 @@ const RowDesc kRows[] = {
     radix32_row_desc(3, 13),
     split_row_desc(3, 14),
     radix32_row_desc(5, 15),
-    RowInst<2048, 128, 8, 4, kNoHoist | kShifted, 16, 16, 8>::desc(0),
+    split_row_desc(5, 0),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd, 16, 16, 8>::desc(1),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane, 16, 16, 8>::desc(2),
     split_row_desc(1, 3),
     RowInst<2048, 128, 8, 4, kNoHoist | kXcd | kPlainLane | kTwPair, 16, 16, 8>::desc(4),
+    RowInst<2048, 128, 8, 4, kNoHoist | kShifted, 16, 16, 8>::desc(5),
 };
 
 template <int R>

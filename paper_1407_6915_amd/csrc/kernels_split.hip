@@ -60,6 +60,9 @@ ColumnDesc split_column_desc(int config, int variant)
     case 4:
         return ColInst<512, 16, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kLdsTw | kTwPair, 32,
                        16>::desc(variant);
+    case 5:
+        return ColInst<2048, 64, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kLdsTw | kTwPair, 16, 16,
+                       8>::desc(variant);
     default:
         return ColumnDesc{};
     }
@@ -81,6 +84,11 @@ RowDesc split_row_desc(int config, int variant)
     case 4:
         return RowInst<512, 16, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kTwPair, 32, 16>::desc(
             variant);
+    case 5:
+        // 16 rows per tile (whole 128-byte lines in the transposed store) fit
+        // the 2048-point row tile's LDS only with split exchanges
+        return RowInst<2048, 64, 16, 4, kSplit | kNoHoist | kXcd | kW4 | kShifted | kTwPair, 16,
+                       16, 8>::desc(variant);
     default:
         return RowDesc{};
     }
