@@ -40,7 +40,7 @@ int frames_enqueue(Plan *p, const c32 *in, c32 *out, uint64_t frames, uint64_t h
     if (p->kind == Plan::SINGLE) {
         // the plan's own kernel variant when it has a frame form, else the
         // length's default frame kernel
-        const SinglePassDesc *d = p->sp && p->sp->launch_strided ? p->sp : find_aux(n);
+        const SinglePassDesc *d = p->sp && p->sp->launch_strided ? p->sp : find_frames(n);
         if (d && d->launch_strided) {
             const uint64_t groups = (frames + d->segs_per_wg - 1) / d->segs_per_wg;
             const unsigned grid = grid_for(d->kernel_strided[p->dir > 0],

@@ -44,8 +44,9 @@ const SinglePassDesc kTable[] = {
     SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 32),
     SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
     // (variant 3 first: the length's frame and real-input kernels are the
-    // first row with them)
-    SpInst<4096, 256, 1, 0, kNT | kPlain | kAux, 16, 16, 16>::desc(3, 32),
+    // first row with them; the frame kernel takes 2.89 ms per 2^18 frames
+    // every 1024 samples at this grid of 16, 2.92-2.98 at 32)
+    SpInst<4096, 256, 1, 0, kNT | kPlain | kAux, 16, 16, 16>::desc(3, 16),
     SpInst<4096, 512, 1, 4, kNT | kPlain | kAux, 8, 8, 8, 8>::desc(2, 64),
     SpInst<4096, 128, 2, 0, kNT | kPlain, 16, 16, 16>::desc(4, 32),
     SpInst<4096, 256, 1, 4, kPlain, 16, 16, 16>::desc(5, 32),
@@ -58,14 +59,18 @@ const SinglePassDesc kTable[] = {
     SpInst<4096, 512, 1, 4, kPrefetch | kNT, 8, 8, 8, 8>::desc(12, 32),
     pad32_desc(0, 13, 64),
     pad32_desc(4, 14, 32),
+    SpInst<4096, 256, 1, 0, kNT | kPlain | kXcdFrames, 16, 16, 16>::desc(15, 32),
     pad32_desc(2, 0, 16),
     SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(1, 32),
     SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(2, 32),
+    // the length's frame kernel (the first row with one): one workgroup per
+    // frame, 3.05 ms per 2^17 frames every 2048 samples against 4.06 through
+    // the real-input row below
+    SpInst<8192, 512, 1, 4, kNT | kNoHoist | kTwPair | kW4 | kFrames, 16, 16, 16, 2>::desc(7, 0),
     SpInst<8192, 512, 1, 4, kNT | kPlain | kAux, 16, 16, 16, 2>::desc(3, 32),
     SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(4, 32),
     SpInst<8192, 512, 1, 4, kPrefetch | kNT, 16, 16, 16, 2>::desc(5, 32),
     SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(6, 16),
-    SpInst<8192, 512, 1, 4, kNT | kNoHoist | kTwPair | kW4, 16, 16, 16, 2>::desc(7, 32),
     split_desc(6, 8, 32),
     split_desc(0, 0, 0),  // one workgroup per segment: 2.95-2.97 ms against 3.19-3.20 at 32
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(1, 32),

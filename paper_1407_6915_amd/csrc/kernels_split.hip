@@ -16,8 +16,8 @@ SinglePassDesc split_desc(int config, int variant, int grid_mult)
     case 0:
         // twiddles read in pairs: 10 table reads per radix-32 butterfly
         // instead of 31 (3.2-3.3 ms per 8 GiB against 4.6 with direct reads)
-        return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair, 16, 32, 32>::desc(
-            variant, grid_mult);
+        return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair | kFrames, 16, 32,
+                      32>::desc(variant, grid_mult);
     case 1:
         return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 32, 32, 16>::desc(
             variant, grid_mult);
@@ -36,8 +36,8 @@ SinglePassDesc split_desc(int config, int variant, int grid_mult)
         return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 16, 32, 32>::desc(
             variant, grid_mult);
     case 6:
-        return SpInst<8192, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair, 16, 16, 32>::desc(
-            variant, grid_mult);
+        return SpInst<8192, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair | kFrames, 16, 16,
+                      32>::desc(variant, grid_mult);
     default:
         return SinglePassDesc{};
     }

@@ -232,6 +232,16 @@ const SinglePassDesc *find_single(uint64_t n, int variant)
 }
 
 // the variant of length n that carries the frame and real-input kernels
+const SinglePassDesc *find_frames(uint64_t n)
+{
+    int cnt = 0;
+    const SinglePassDesc *t = single_pass_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if ((uint64_t)t[i].n == n && t[i].launch_strided)
+            return &t[i];
+    return nullptr;
+}
+
 const SinglePassDesc *find_aux(uint64_t n)
 {
     int cnt = 0;

@@ -60,6 +60,8 @@ const char *last_message();
 c32 root_forward(uint64_t m, uint64_t n);
 const SinglePassDesc *find_single(uint64_t n, int variant);
 const SinglePassDesc *find_aux(uint64_t n);
+// the length's default frame kernel: the first row of n with one
+const SinglePassDesc *find_frames(uint64_t n);
 int variant_count(uint64_t n);
 // n1: the column length to use (0: the planner's balanced choice)
 bool find_split(uint64_t n, const ColumnDesc **col, const RowDesc **row, int col_variant,

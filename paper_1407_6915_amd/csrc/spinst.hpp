@@ -22,11 +22,15 @@ namespace sp {
 // policy); kSplit = the kernel with split (real, then imaginary) LDS
 // exchanges; kW4 / kW8 = 4 / 8 waves per SIMD; kIndexed = the row also
 // provides the kernel over segments at listed offsets; kTwPair = stages that
-// reload their twiddles read them as pairs (tw_pair_low).
+// reload their twiddles read them as pairs (tw_pair_low); kFrames = the row
+// also provides a frame kernel (not the real-input ones); kXcdFrames = its
+// frame kernel deals the frames to the XCDs in contiguous runs.  Frame
+// kernels read overlapping frames through the cache
+// (single_pass_strided_kernel).
 constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
               kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256,
               kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096, kIndexed = 8192,
-              kTwPair = 16384;
+              kTwPair = 16384, kFrames = 32768, kXcdFrames = 65536;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -47,7 +51,7 @@ struct SpInst {
                                  (F & kPlainLds) != 0, (F & (kClassic | kPrefetch)) != 0,
                                  (F & kSplit) != 0, (F & kTwPair) != 0>;
     static_assert(!((F & kSplit) && (F & (kAux | kClassic))),
-                  "split exchanges: transform kernels only");
+                  "split exchanges: transform and frame kernels only");
 
     using kernel_fn = void (*)(const c32 *, c32 *, const c32 *, uint64_t);
     template <int D>
@@ -75,19 +79,20 @@ struct SpInst {
             hipLaunchKernelGGL(kernel<1>(), g, b, 0, s, (const c32 *)in, (c32 *)out,
                                (const c32 *)tw, batch);
     }
+    static constexpr int kFrameMode = (F & kXcdFrames) ? 3 : 1;
     static void launch_strided(int dir, const void *in, void *out, const void *tw,
                                uint64_t batch, uint64_t in_stride, uint64_t out_stride,
                                const float *window, unsigned grid, hipStream_t s)
     {
         const dim3 g(grid), b(Pol::kThreads);
         if (dir < 0)
-            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, -1>), g, b, 0, s,
-                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch, in_stride,
-                               out_stride, window);
+            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, -1, kFrameMode>), g, b, 0,
+                               s, (const c32 *)in, (c32 *)out, (const c32 *)tw, batch,
+                               in_stride, out_stride, window);
         else
-            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, 1>), g, b, 0, s,
-                               (const c32 *)in, (c32 *)out, (const c32 *)tw, batch, in_stride,
-                               out_stride, window);
+            hipLaunchKernelGGL((single_pass_strided_kernel<Sh, Pol, 1, kFrameMode>), g, b, 0,
+                               s, (const c32 *)in, (c32 *)out, (const c32 *)tw, batch,
+                               in_stride, out_stride, window);
     }
     static void launch_real(int dir, const void *in, void *out, const void *tw, const void *hw,
                             uint64_t batch, unsigned grid, hipStream_t s)
@@ -136,10 +141,14 @@ struct SpInst {
             d.kernel_indexed[0] = (const void *)&single_pass_indexed_kernel<Sh, Pol, -1>;
             d.kernel_indexed[1] = (const void *)&single_pass_indexed_kernel<Sh, Pol, 1>;
         }
-        if constexpr ((F & kAux) != 0) {
+        if constexpr ((F & (kAux | kFrames | kXcdFrames)) != 0) {
             d.launch_strided = &launch_strided;
-            d.kernel_strided[0] = (const void *)&single_pass_strided_kernel<Sh, Pol, -1>;
-            d.kernel_strided[1] = (const void *)&single_pass_strided_kernel<Sh, Pol, 1>;
+            d.kernel_strided[0] =
+                (const void *)&single_pass_strided_kernel<Sh, Pol, -1, kFrameMode>;
+            d.kernel_strided[1] =
+                (const void *)&single_pass_strided_kernel<Sh, Pol, 1, kFrameMode>;
+        }
+        if constexpr ((F & kAux) != 0) {
             d.launch_real = &launch_real;
             d.kernel_real[0] = (const void *)&real_forward_kernel<Sh, Pol>;
             d.kernel_real[1] = (const void *)&real_inverse_kernel<Sh, Pol>;

@@ -538,20 +538,47 @@ __device__ __forceinline__ void single_tile(c32 *lds, const c32 *__restrict__ tw
         tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
+// Tile order of a persistent grid.  Workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup w on XCD w % 8); with Xcd the tiles of one
+// sweep are dealt so that the workgroups of one XCD take consecutive tiles,
+// so adjacent column blocks -- the two halves of the same cache lines --
+// are read through the same L2 at about the same time.
+template <bool Xcd>
+__device__ __forceinline__ uint64_t tile_of(uint64_t sweep_base, unsigned w, unsigned grid)
+{
+    if constexpr (Xcd) {
+        if ((grid & 7u) == 0)
+            return sweep_base + (uint64_t)(w & 7u) * (grid >> 3) + (w >> 3);
+    }
+    return sweep_base + w;
+}
+
 // Overlapping, windowed segments (short-time transform): segment s reads
 // x_s[n] = in[s * in_stride + n] * window[n] (window may be null) and writes
 // its spectrum at out + s * out_stride.
 template <class Sh, class Pol, int D>
 __device__ __forceinline__ void windowed_tile(c32 *lds, const c32 *__restrict__ tw, int tid,
                                               int tid_tw, const c32 *x, c32 *y, bool valid,
-                                              const float *__restrict__ window)
+                                              const float *__restrict__ window, bool cached)
 {
     const int t = Pol::template thr<0>(tid);
     typename Pol::Ctx ctx{y, valid && Pol::active(tid)};
     c32 v[Sh::kMaxE];
     using S0 = Stage<Sh, 0, 1>;
     if (ctx.valid) {
-        if (window) {
+        if (cached) {
+            // overlapping frames: the samples a frame shares with the next
+            // ones stay in L2 for them
+            if (window) {
+                st_gather<S0, Sh>(v, t, [&](int i) {
+                    const c32 a = gload<false>(x + i);
+                    const float w = window[i];
+                    return c32{a.x * w, a.y * w};
+                });
+            } else {
+                st_gather<S0, Sh>(v, t, [&](int i) { return gload<false>(x + i); });
+            }
+        } else if (window) {
             st_gather<S0, Sh>(v, t, [&](int i) {
                 const c32 a = gload<Pol::kNT>(x + i);
                 const float w = window[i];
@@ -561,26 +588,42 @@ __device__ __forceinline__ void windowed_tile(c32 *lds, const c32 *__restrict__ 
             st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(x + i); });
         }
     }
-    if constexpr (Pol::kClassic)
+    // lds holds lds_c32<kLdsElems, kSplit>() complex elements
+    if constexpr (Pol::kSplit)
+        tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid, tid_tw,
+                                         ctx);
+    else if constexpr (Pol::kClassic)
         tile_run_plain<Sh, Pol, D, 0, 1>(v, lds, tw, tid, ctx);
     else
         tile_run<Sh, Pol, D, 0, 1>(v, lds, tw, tid, tid_tw, ctx);
 }
 
-template <class Sh, class Pol, int D>
-__global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
+// Mode bit 0: frames that overlap (in_stride < M) are read through the
+// cache even where the policy streams (4096-point frames every 1024
+// samples: 2.89 ms per 2^18 frames against 3.19 streamed); bit 1: each XCD
+// takes a contiguous run of frame groups per sweep of the grid (tile_of),
+// so the frames that share samples are read through the same L2 (a quarter
+// of the HBM reads, but 2.99 ms).  These forms hold at least two waves per
+// SIMD (the window and stride arguments would otherwise push a 252-register
+// tile past half the register file).
+template <class Sh, class Pol, int D, int Mode = 0>
+__global__ void __launch_bounds__(Pol::kThreads)
+    __attribute__((amdgpu_waves_per_eu(Mode != 0 && Pol::kWaves < 2 ? 2 : Pol::kWaves)))
     single_pass_strided_kernel(const c32 *in, c32 *out, const c32 *__restrict__ tw,
                                uint64_t batch, uint64_t in_stride, uint64_t out_stride,
                                const float *__restrict__ window)
 {
-    __shared__ c32 lds[Pol::kLdsElems];
+    __shared__ c32 lds[lds_c32<Pol::kLdsElems, Pol::kSplit>()];
     const int tid_tw = threadIdx.x;
     const uint64_t groups = (batch + Pol::S - 1) / Pol::S;
-    for (uint64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const bool cached = (Mode & 1) && in_stride < (uint64_t)Sh::M;
+    // tile_of(base, w, grid) is base plus a permutation of the workgroups
+    for (uint64_t g = tile_of<(Mode & 2) != 0>(0, blockIdx.x, gridDim.x); g < groups;
+         g += gridDim.x) {
         const int tid = Pol::kPlainLane ? tid_tw : opaque_lane();
         const uint64_t seg = g * Pol::S + Pol::template col<0>(tid);
         windowed_tile<Sh, Pol, D>(lds, tw, tid, tid_tw, in + seg * in_stride,
-                                  out + seg * out_stride, seg < batch, window);
+                                  out + seg * out_stride, seg < batch, window, cached);
     }
 }
 
@@ -948,21 +991,6 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
 // of one segment, so every global access moves runs of C*8 contiguous bytes.
 // W_N^m (m = n2*k1 < N) is the product of two table entries
 // th[m >> sh] * tl[m & (2^sh - 1)], each evaluated in FP64 and rounded once.
-
-// Tile order of a persistent grid.  Workgroups are dispatched round-robin
-// over the 8 XCDs (workgroup w on XCD w % 8); with Xcd the tiles of one
-// sweep are dealt so that the workgroups of one XCD take consecutive tiles,
-// so adjacent column blocks -- the two halves of the same cache lines --
-// are read through the same L2 at about the same time.
-template <bool Xcd>
-__device__ __forceinline__ uint64_t tile_of(uint64_t sweep_base, unsigned w, unsigned grid)
-{
-    if constexpr (Xcd) {
-        if ((grid & 7u) == 0)
-            return sweep_base + (uint64_t)(w & 7u) * (grid >> 3) + (w >> 3);
-    }
-    return sweep_base + w;
-}
 
 // Y between the two passes: in the input's layout, Y[k1][n2] at k1 N2 + n2,
 // or (policies with YBlk) in blocks of kYBlock columns, at

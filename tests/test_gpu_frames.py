@@ -147,3 +147,27 @@ def test_two_pass_frames_across_sub_batches():
         got = y[f * n:(f + 1) * n].cpu().numpy()[None]
         ref = oracle.short_time(x[f * hop:f * hop + n], n, hop, 1, w)
         assert oracle.rel_l2(got, ref)[0] <= oracle.tolerance(n), f
+
+
+@pytest.mark.parametrize("n,hop,frames,variant", [
+    (4096, 1024, 1601, 3),     # the length's frame kernel (cached overlapping loads)
+    (4096, 1024, 1601, 15),    # frames dealt to the XCDs in contiguous runs
+    (4096, 4096, 901, 3),      # disjoint frames: streamed loads
+    (8192, 2048, 701, 7),
+    (16384, 4096, 701, 0),     # split exchanges
+])
+def test_frame_kernels_walk_several_groups(monkeypatch, n, hop, frames, variant):
+    """Frame kernels on a persistent grid of one resident wave of workgroups:
+    each workgroup takes several frame groups and the last sweep is ragged."""
+    import torch
+    monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
+    announce("frames walk n=%d hop=%d frames=%d variant=%d" % (n, hop, frames, variant))
+    x = siggen.Signal(seed=47, seg_len=1, sigma=1.0).samples(0, (frames - 1) * hop + n)
+    w = hann32(n)
+    xd = torch.from_numpy(x).to("cuda")
+    wd = torch.from_numpy(w).to("cuda")
+    with fs.Plan(n, frames, fs.FORWARD, variant) as p:
+        assert p.describe()["grid_mult"] == 1
+        y = p.exec_frames(xd, hop, frames, wd).cpu().numpy().reshape(frames, n)
+    err = oracle.rel_l2(y, oracle.short_time(x, n, hop, frames, w))
+    assert np.all(err <= oracle.tolerance(n)), float(err.max())
