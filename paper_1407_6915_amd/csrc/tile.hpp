@@ -1251,16 +1251,24 @@ __global__ void __launch_bounds__(Pol::kThreads) __attribute__((amdgpu_waves_per
         column_lds_twiddles<Sh, Pol>(lds, ctx, par, tid);
         c32 v[Sh::kMaxE];
         const c32 *xc = in + seg * hop + first + c;
-        if (window) {
-            const float *wc = window + first + c;
-            st_gather<S0, Sh>(v, t, [&](int i) {
-                const c32 a = gload<Pol::kNT>(xc + (size_t)i * n2);
-                const float w = wc[(size_t)i * n2];
-                return c32{a.x * w, a.y * w};
-            });
-        } else {
-            st_gather<S0, Sh>(v, t, [&](int i) { return gload<Pol::kNT>(xc + (size_t)i * n2); });
-        }
+        // overlapping frames are loaded through the cache (as in
+        // single_pass_strided_kernel)
+        auto gather = [&](auto load) {
+            if (window) {
+                const float *wc = window + first + c;
+                st_gather<S0, Sh>(v, t, [&](int i) {
+                    const c32 a = load(xc + (size_t)i * n2);
+                    const float w = wc[(size_t)i * n2];
+                    return c32{a.x * w, a.y * w};
+                });
+            } else {
+                st_gather<S0, Sh>(v, t, [&](int i) { return load(xc + (size_t)i * n2); });
+            }
+        };
+        if (hop < nseg)
+            gather([](const c32 *p) { return gload<false>(p); });
+        else
+            gather([](const c32 *p) { return gload<Pol::kNT>(p); });
         if constexpr (Pol::kSplit)
             tile_run_split<Sh, Pol, D, 0, 1>(v, reinterpret_cast<float *>(lds), tw, tid,
                                              threadIdx.x, ctx);
