@@ -60,7 +60,7 @@ const SinglePassDesc kTable[] = {
     pad32_desc(0, 13, 64),
     pad32_desc(4, 14, 32),
     SpInst<4096, 256, 1, 0, kNT | kPlain | kXcdFrames, 16, 16, 16>::desc(15, 32),
-    pad32_desc(2, 0, 16),
+    pad32_desc(2, 8, 16),
     SpInst<8192, 512, 1, 4, kClassic, 16, 16, 16, 2>::desc(1, 32),
     SpInst<8192, 512, 1, 4, kPlain, 16, 16, 16, 2>::desc(2, 32),
     // the length's frame kernel (the first row with one): one workgroup per
@@ -71,7 +71,9 @@ const SinglePassDesc kTable[] = {
     SpInst<8192, 256, 1, 4, kNT | kNoHoist, 32, 16, 16>::desc(4, 32),
     SpInst<8192, 512, 1, 4, kPrefetch | kNT, 16, 16, 16, 2>::desc(5, 32),
     SpInst<8192, 512, 1, 4, kPrefetch, 16, 16, 16, 2>::desc(6, 16),
-    split_desc(6, 8, 32),
+    // split exchanges, paired twiddle reads, one workgroup per segment: 2.99-3.01
+    // ms per 8 GiB against 3.20-3.28 for the prefetch kernel (variant 8)
+    split_desc(6, 0, 0),
     split_desc(0, 0, 0),  // one workgroup per segment: 2.95-2.97 ms against 3.19-3.20 at 32
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist | kPlain | kAux, 16, 16, 16, 4>::desc(1, 32),
     SpInst<16384, 1024, 1, 4, kNT | kNoHoist, 16, 16, 16, 4>::desc(2, 32),

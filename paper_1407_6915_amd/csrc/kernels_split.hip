@@ -36,8 +36,8 @@ SinglePassDesc split_desc(int config, int variant, int grid_mult)
         return SpInst<16384, 512, 1, 4, kSplit | kNT | kNoHoist | kW4, 16, 32, 32>::desc(
             variant, grid_mult);
     case 6:
-        return SpInst<8192, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair | kFrames, 16, 16,
-                      32>::desc(variant, grid_mult);
+        return SpInst<8192, 512, 1, 4, kSplit | kNT | kNoHoist | kW4 | kTwPair, 16, 16, 32>::desc(
+            variant, grid_mult);
     default:
         return SinglePassDesc{};
     }
