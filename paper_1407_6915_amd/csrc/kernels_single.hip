@@ -30,17 +30,29 @@ const SinglePassDesc kTable[] = {
     SpInst<512, 64, 4, 4, kPlain, 8, 8, 8>::desc(1, 32),
     SpInst<512, 32, 8, 4, kNT | kPlain, 16, 16, 2>::desc(2, 64),
     SpInst<512, 64, 4, 4, kClassic | kNT | kAux, 8, 8, 8>::desc(3, 32),
-    SpInst<1024, 64, 2, 4, kNT | kPlain | kAux, 16, 16, 4>::desc(0, 64),
+    SpInst<512, 16, 16, 4, kClassic | kNT, 32, 16>::desc(4, 32),
+    SpInst<1024, 64, 2, 4, kNT | kPlain | kAux | kSmallBatch, 16, 16, 4>::desc(7, 64),
     SpInst<1024, 64, 4, 4, kNT | kPlain, 16, 16, 4>::desc(1, 64),
     SpInst<1024, 64, 4, 4, kPlain, 16, 16, 4>::desc(2, 32),
     SpInst<1024, 64, 4, 4, kNT, 16, 16, 4>::desc(3, 32),
     SpInst<1024, 64, 4, 4, kClassic, 16, 16, 4>::desc(4, 32),
     pad32_desc(1, 5, 64),
-    SpInst<2048, 128, 1, 4, kNT | kPlain | kAux, 16, 16, 8>::desc(0, 64),
+    SpInst<1024, 64, 4, 4, kClassic | kNT, 16, 16, 4>::desc(6, 32),
+    // radix 32, eight segments per workgroup: 2.83-2.85 ms per 8 GiB against
+    // 3.03-3.04 for the radix-16 kernel of variant 7, which small batches take
+    // (1024 segments: 128 workgroups of this kernel)
+    SpInst<1024, 32, 8, 4, kClassic | kNT, 32, 32>::desc(0, 32),
+    SpInst<1024, 32, 4, 4, kClassic | kNT, 32, 32>::desc(8, 32),
+    SpInst<1024, 32, 16, 4, kClassic | kNT, 32, 32>::desc(9, 32),
+    SpInst<2048, 128, 1, 4, kNT | kPlain | kAux | kSmallBatch, 16, 16, 8>::desc(6, 64),
     SpInst<2048, 128, 2, 4, kNT | kPlain, 16, 16, 8>::desc(1, 64),
     SpInst<2048, 128, 2, 4, kPlain, 16, 16, 8>::desc(2, 32),
     SpInst<2048, 128, 2, 4, kClassic, 16, 16, 8>::desc(3, 32),
     pad32_desc(3, 4, 64),
+    SpInst<2048, 128, 2, 4, kClassic | kNT, 16, 16, 8>::desc(5, 32),
+    // 2.86-2.87 ms per 8 GiB against 2.99-3.04 for the 16-16-8 kernel of variant 6
+    // (small batches)
+    SpInst<2048, 64, 4, 4, kClassic | kNT, 32, 8, 8>::desc(0, 32),
     SpInst<4096, 128, 2, 4, kClassic | kNT, 16, 16, 16>::desc(0, 32),
     SpInst<4096, 128, 2, 4, kClassic, 16, 16, 16>::desc(1, 64),
     // (variant 3 first: the length's frame and real-input kernels are the

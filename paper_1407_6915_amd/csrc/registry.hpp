@@ -56,6 +56,8 @@ struct SinglePassDesc {
     int grid_mult;      // default persistent grid: resident waves of workgroups
     int lds_bytes;
     int shuffle;        // 1: an exchange between stages runs through lane shuffles
+    int small_batch;    // 1: the length's kernel for batches that give the default
+                        //    fewer than two workgroups per CU
     int nrad;
     int radices[kMaxRadices];
     sp_launch_fn launch;

@@ -232,6 +232,16 @@ const SinglePassDesc *find_single(uint64_t n, int variant)
 }
 
 // the variant of length n that carries the frame and real-input kernels
+static const SinglePassDesc *find_small_batch(uint64_t n)
+{
+    int cnt = 0;
+    const SinglePassDesc *t = single_pass_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if ((uint64_t)t[i].n == n && t[i].small_batch)
+            return &t[i];
+    return nullptr;
+}
+
 const SinglePassDesc *find_frames(uint64_t n)
 {
     int cnt = 0;
@@ -465,12 +475,22 @@ int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant
         p->kind = Plan::COPY;
         return set_ok();
     }
-    int variant = forced_variant >= 0 ? forced_variant : tuned_variant(n);
+    const int tuned = forced_variant >= 0 ? -1 : tuned_variant(n);
+    int variant = forced_variant >= 0 ? forced_variant : tuned;
     if (variant < 0)
         variant = 0;
     p->sp = find_single(n, variant);
     if (!p->sp && forced_variant < 0)
         p->sp = find_single(n, 0);
+    if (p->sp && forced_variant < 0 && tuned < 0) {
+        // a batch that gives the default kernel fewer than two workgroups
+        // per CU takes the length's small-batch kernel, if it has one
+        const SinglePassDesc *alt = find_small_batch(n);
+        const uint64_t groups =
+            (batch + (uint64_t)p->sp->segs_per_wg - 1) / (uint64_t)p->sp->segs_per_wg;
+        if (alt && groups < 2 * (uint64_t)device_cus(p->device))
+            p->sp = alt;
+    }
     if (forced_variant >= 0 && !p->sp)
         return set_error(FFT_ERR_INVALID_ARG, "length %llu has no variant %d",
                          (unsigned long long)n, forced_variant);

@@ -26,11 +26,12 @@ namespace sp {
 // also provides a frame kernel (not the real-input ones); kXcdFrames = its
 // frame kernel deals the frames to the XCDs in contiguous runs.  Frame
 // kernels read overlapping frames through the cache
-// (single_pass_strided_kernel).
+// (single_pass_strided_kernel).  kSmallBatch = the planner's choice for
+// batches too small to give the default kernel two workgroups per CU.
 constexpr int kNT = 1, kNoHoist = 2, kHoistLast = 4, kW2 = 8, kW3 = 16, kPlainLane = 32,
               kPlainLds = 64, kPlain = kPlainLane | kPlainLds, kClassic = 128, kAux = 256,
               kPrefetch = 512, kSplit = 1024, kW4 = 2048, kW8 = 4096, kIndexed = 8192,
-              kTwPair = 16384, kFrames = 32768, kXcdFrames = 65536;
+              kTwPair = 16384, kFrames = 32768, kXcdFrames = 65536, kSmallBatch = 131072;
 
 template <int NS, int F>
 constexpr int hoist_mask()
@@ -127,6 +128,7 @@ struct SpInst {
         d.segs_per_wg = S;
         d.pad_shift = PS;
         d.nontemporal = (F & kNT) != 0;
+        d.small_batch = (F & kSmallBatch) != 0;
         d.hoist = hoist_mask<sizeof...(Rs), F>();
         d.lds_bytes = Pol::kLdsElems * (int)((F & kSplit) ? sizeof(float) : sizeof(c32));
         d.nrad = (int)sizeof...(Rs);

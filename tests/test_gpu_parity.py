@@ -364,6 +364,26 @@ def test_plan_describe():
     assert d["kind"] == "radix_stages"
 
 
+def test_small_batches_take_the_small_batch_kernel():
+    """A batch that gives a length's default kernel fewer than two
+    workgroups per CU takes the length's small-batch kernel, unless a
+    variant is forced; both agree with the oracle."""
+    import torch
+    announce("small-batch kernels")
+    for n, small, large, small_variant in [(1024, 1024, 1 << 16, 7), (2048, 256, 1 << 14, 6)]:
+        with fs.Plan(n, small) as p:
+            assert p.describe()["variant"] == small_variant
+        with fs.Plan(n, large) as p:
+            assert p.describe()["variant"] == 0
+        with fs.Plan(n, small, fs.FORWARD, 0) as p:
+            assert p.describe()["variant"] == 0
+        x = noise(n, small, seed=n + 5)
+        ref = oracle.fft_recursive(x, n)
+        with fs.Plan(n, small) as p:
+            y = p.exec(torch.from_numpy(x.reshape(-1)).cuda()).cpu().numpy().reshape(small, n)
+        assert np.all(oracle.rel_l2(y, ref) <= oracle.tolerance(n))
+
+
 @pytest.mark.parametrize("n,b,sub", [(1 << 16, 7, 2), (1 << 18, 5, 2), (1 << 20, 5, 2)])
 @pytest.mark.parametrize("lead", [0, 3])
 def test_two_pass_plans_across_sub_batches(monkeypatch, n, b, sub, lead):
