@@ -75,7 +75,10 @@ typedef struct fftseg_plan *fft_plan_t;
 /* Build a plan for `batch` segments of `segment_len` samples in direction
  * FFT_FORWARD or FFT_INVERSE.  Factorises the length, picks the kernel (one
  * LDS-resident pass up to 16384 samples, a two-pass "four-step" split
- * N = N1*N2 above, a radix-by-radix fallback otherwise), uploads the
+ * N = N1*N2 above, a radix-by-radix fallback otherwise; a tuned choice
+ * first, and for a batch that would give the length's default one-pass
+ * kernel fewer than two workgroups per CU, the length's small-batch
+ * kernel where it has one), uploads the
  * twiddle tables (evaluated in FP64, rounded once to float32) and allocates
  * the scratch of two-pass plans.  Returns NULL on error.  Validation:
  * segment_len == 0, batch == 0, batch*segment_len*8 overflowing size_t or
@@ -264,8 +267,9 @@ int fft_host_free(void *ptr);
  * 1 <= n_frames <= the plan's batch and hop >= 1, else
  * FFT_ERR_INVALID_ARG.  Lengths with a one-pass kernel read the frames in
  * place (with the plan's own kernel variant when it has a frame form, else
- * the length's default frame kernel); other lengths gather the windowed
- * frames into out first and transform out in place. */
+ * the length's default frame kernel; overlapping frames are loaded through
+ * the cache), two-pass lengths in their first pass; other lengths gather
+ * the windowed frames into out first and transform out in place. */
 int fft_exec_frames(fft_plan_t plan, const void *in, size_t in_len, void *out,
                     size_t n_frames, size_t hop, const float *window, void *stream);
 
