@@ -432,7 +432,7 @@ int fft_autotune(size_t segment_len, size_t batch, int direction, const char *pa
                  double *best_us);
 
 /* Load a cache written by fft_autotune for this device's architecture;
- * entries naming variants or splits this build lacks are skipped.  Returns
+ * entries naming variants or splits the library lacks are skipped.  Returns
  * the number of entries loaded. */
 int fft_tune_load(const char *path);
 

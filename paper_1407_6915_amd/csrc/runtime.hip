@@ -511,7 +511,7 @@ int plan_choose(Plan *p, uint64_t n, uint64_t batch, int dir, int forced_variant
     }
     bool split = find_split(n, &p->col, &p->row, cv, rv, n1);
     if (!split && n1 && !forced_n1)
-        split = find_split(n, &p->col, &p->row, 0, 0, 0);  // a tuned split this build lacks
+        split = find_split(n, &p->col, &p->row, 0, 0, 0);  // a tuned split the library lacks
     if (!split && forced_n1)
         return set_error(FFT_ERR_INVALID_ARG, "length %llu has no split with %llu columns",
                          (unsigned long long)n, (unsigned long long)forced_n1);

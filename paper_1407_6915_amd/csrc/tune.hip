@@ -413,10 +413,10 @@ extern "C" int fft_tune_load(const char *path)
                 g > 1024 ||
                 (v < 0 && (cv < 0 || rv < 0 || (ncol && cv >= ncol) || (nrow && rv >= nrow))) ||
                 n1 < 0 || (n1 > 0 && !find_split((uint64_t)n, &sc, &sr, 0, 0, (uint64_t)n1)))
-                continue;  // stale entry for variants this build does not have
+                continue;  // stale entry for variants the library does not have
             const int n_idx = fft_worklist_indexed_count((uint32_t)n);
             if (wr < -1 || wr > n_idx || wg < 0 || wg > 1024)
-                wr = -1, wg = 0;  // a work-list route this build does not have
+                wr = -1, wg = 0;  // a work-list route the library does not have
             read_number(o, "us", &us);
             read_number(o, "batch", &b);
             TunedChoice c{(uint64_t)n, (int)v, (int)g, us, (uint64_t)b, (int)cv, (int)rv,
