@@ -36,6 +36,8 @@ def run_frames(n, x, hop, n_frames, window, direction=fs.FORWARD, batch=None):
     (4096, 4099, 5),        # gaps between frames
     (1000, 333, 17),        # non power of two, odd hop
     (16384, 8192, 7),
+    (8192, 2048, 9),        # the length's frame kernel is not its default's
+    (2048, 512, 11),
     (1 << 16, 1 << 14, 5),  # two-pass lengths: read by the column pass
     (1 << 15, 1000, 6),
     (1 << 18, 70001, 4),
