@@ -10,6 +10,8 @@
 // once per frame and nothing is staged; the radix-stage lengths first
 // gather the windowed frames into the output buffer and transform it in
 // place.
+#include <stdlib.h>
+
 #include "fftseg.h"
 #include "runtime.hpp"
 
@@ -39,13 +41,14 @@ int frames_enqueue(Plan *p, const c32 *in, c32 *out, uint64_t frames, uint64_t h
     const uint64_t n = p->n;
     if (p->kind == Plan::SINGLE) {
         // the plan's own kernel variant when it has a frame form, else the
-        // length's default frame kernel
+        // length's default frame kernel (at its own grid, unless the
+        // FFTSEG_GRID_MULT override set the plan's)
         const SinglePassDesc *d = p->sp && p->sp->launch_strided ? p->sp : find_frames(n);
         if (d && d->launch_strided) {
             const uint64_t groups = (frames + d->segs_per_wg - 1) / d->segs_per_wg;
+            const int gm = d == p->sp || getenv("FFTSEG_GRID_MULT") ? p->grid_mult : d->grid_mult;
             const unsigned grid = grid_for(d->kernel_strided[p->dir > 0],
-                                           d->threads * d->segs_per_wg, groups, p->device,
-                                           d == p->sp ? p->grid_mult : d->grid_mult);
+                                           d->threads * d->segs_per_wg, groups, p->device, gm);
             d->launch_strided(p->dir, in, out, p->tw, frames, hop, n, window, grid, s);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess)

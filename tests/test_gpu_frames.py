@@ -157,13 +157,15 @@ def test_two_pass_frames_across_sub_batches():
     (4096, 4096, 901, 3),      # disjoint frames: streamed loads
     (8192, 2048, 701, 7),
     (16384, 4096, 701, 0),     # split exchanges
+    (4096, 1024, 1601, None),  # default plans: the frame kernel of another row
+    (8192, 2048, 701, None),
 ])
 def test_frame_kernels_walk_several_groups(monkeypatch, n, hop, frames, variant):
     """Frame kernels on a persistent grid of one resident wave of workgroups:
     each workgroup takes several frame groups and the last sweep is ragged."""
     import torch
     monkeypatch.setenv("FFTSEG_GRID_MULT", "1")
-    announce("frames walk n=%d hop=%d frames=%d variant=%d" % (n, hop, frames, variant))
+    announce("frames walk n=%d hop=%d frames=%d variant=%s" % (n, hop, frames, variant))
     x = siggen.Signal(seed=47, seg_len=1, sigma=1.0).samples(0, (frames - 1) * hop + n)
     w = hann32(n)
     xd = torch.from_numpy(x).to("cuda")
