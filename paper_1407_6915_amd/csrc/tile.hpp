@@ -603,9 +603,9 @@ __device__ __forceinline__ void windowed_tile(c32 *lds, const c32 *__restrict__ 
 // samples: 2.89 ms per 2^18 frames against 3.19 streamed); bit 1: each XCD
 // takes a contiguous run of frame groups per sweep of the grid (tile_of),
 // so the frames that share samples are read through the same L2 (a quarter
-// of the HBM reads, but 2.99 ms).  These forms hold at least two waves per
-// SIMD (the window and stride arguments would otherwise push a 252-register
-// tile past half the register file).
+// of the HBM reads, but 2.99 ms).  These forms ask for at least two waves
+// per SIMD, so the window and stride registers cannot push a kernel down to
+// one.
 template <class Sh, class Pol, int D, int Mode = 0>
 __global__ void __launch_bounds__(Pol::kThreads)
     __attribute__((amdgpu_waves_per_eu(Mode != 0 && Pol::kWaves < 2 ? 2 : Pol::kWaves)))
