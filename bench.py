@@ -214,14 +214,15 @@ def main():
                     help="also time a plain device copy of the same size")
     ap.add_argument("--workload", default="large",
                     choices=["large", "small", "uneven", "streamed", "serving", "long",
-                             "real", "frames", "file", "lengths"],
+                             "real", "frames", "file", "lengths", "frame_lengths"],
                     help="large = the 4096-point x 262144 batch (the reported metric); "
                          "the others print their own JSON line")
     ap.add_argument("--chunks", type=int, default=64, help="streamed: chunks of 4 GiB")
     ap.add_argument("--no-tune", action="store_true",
                     help="uneven: skip the autotuned run (for profiling the default one)")
     ap.add_argument("--lengths", default="16384,6000,4096,1000",
-                    help="lengths: segment lengths to time, 8 GiB each")
+                    help="lengths: segment lengths to time, 8 GiB each (frame_lengths: "
+                         "frames every N/4 samples of a 2^28-sample signal)")
     ap.add_argument("--file-gib", type=int, default=16,
                     help="file: size of the signal file (GiB; shrunk to the free space)")
     ap.add_argument("--file-dir", default="", help="file: directory (default $TMPDIR or /tmp)")

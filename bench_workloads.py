@@ -556,6 +556,36 @@ def frames(args):
     return 0
 
 
+def frame_lengths(args):
+    """Frames of each listed length every N/4 samples (75 % overlap) of a
+    2^28-sample signal with a periodic Hann window: the frame kernel of every
+    one-pass length, or the column pass of two-pass lengths."""
+    import torch
+    import paper_1407_6915_amd as fs
+    total = 1 << 28
+    g = torch.Generator(device="cuda").manual_seed(0x14076917)
+    x = torch.randn(total, dtype=torch.complex64, device="cuda", generator=g)
+    sh = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for n in [int(v) for v in args.lengths.split(",")]:
+        hop = max(1, n // 4)
+        nf = (total - n) // hop + 1
+        j = torch.arange(n, dtype=torch.float64, device="cuda")
+        w = (0.5 - 0.5 * torch.cos(2 * math.pi * j / n)).float()
+        y = torch.empty(nf * n, dtype=torch.complex64, device="cuda")
+        with fs.Plan(n, nf) as p:
+            t = _time(torch, lambda: p.exec_frames_ptr(x.data_ptr(), total, y.data_ptr(), nf,
+                                                       hop, w.data_ptr(), sh), args.steps)
+            kind = p.describe()["kind"]
+        rows.append({"segment_len": n, "hop": hop, "frames": nf, "kind": kind,
+                     "ms": round(t * 1e3, 3), "GFLOP/s": round(FLOP(n) * nf / t / 1e9, 1),
+                     "frame_bytes_GBps": round(16.0 * nf * n / t / 1e9, 1)})
+        del y
+    print(json.dumps({"workload": "frame_lengths_hop_quarter_hann", "signal_samples": total,
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def lengths(args):
     """Plain batched plans of the listed lengths, each over 8 GiB resident in
     HBM (the kernel-level rates behind the one-pass and two-pass rows; a
@@ -694,4 +724,5 @@ def file(args):
 def run(args):
     return {"small": small, "uneven": uneven, "streamed": streamed,
             "serving": serving, "long": long, "real": real,
-            "frames": frames, "file": file, "lengths": lengths}[args.workload](args)
+            "frames": frames, "file": file, "lengths": lengths,
+            "frame_lengths": frame_lengths}[args.workload](args)
